@@ -1,0 +1,155 @@
+"""Pins of the oracle's solve, potential, force, leapfrog and Hamiltonian.
+
+The force is pinned to central finite differences of the exact-solve potential (which pins the
+frozen-x evaluation and its sign); the integrator to reversibility, second order and volume
+preservation; the identity behind the auxiliary variable to quadrature.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gp, hmc, posterior
+from paper_2412_20884_amd import inputs as I
+
+
+def _problem(n=24, d=2, seed=3, kind="iso"):
+    if kind == "iso":
+        p = I.iso_problem(n, d, seed, ell=0.35, sigma2=0.05)
+    else:
+        p = I.ard_problem(n, d, seed, sigma2=0.05)
+    X, y, th = p["X"], p["y"], p["theta"]
+    phi = np.random.default_rng(seed).normal(size=n) * 0.5
+    return X, y, th, phi
+
+
+def test_solve_residual():
+    X, y, th, _ = _problem()
+    x = hmc.solve(X, th, "iso", y)
+    np.testing.assert_allclose(gp.a_matrix(X, th, "iso") @ x, y, atol=1e-11)
+
+
+@pytest.mark.parametrize("kind,d", [("iso", 2), ("ard", 3)])
+def test_force_is_gradient_of_potential(kind, d):
+    X, y, th, phi = _problem(d=d, kind=kind)
+    F = hmc.force(X, th, kind, y, phi)
+    h = 1e-5
+    for p in range(len(th)):
+        e = np.zeros_like(th)
+        e[p] = h
+        fd = (hmc.potential(X, th + e, kind, y, phi) - hmc.potential(X, th - e, kind, y, phi)) / (2 * h)
+        assert abs(F[p] - fd) <= 1e-7 * max(1.0, abs(fd)), (p, F[p], fd)
+
+
+def test_variational_energy_form():
+    X, y, th, phi = _problem()
+    x = hmc.solve(X, th, "iso", y)
+    U = hmc.potential(X, th, "iso", y, phi)
+    assert abs(hmc.potential_at(X, th, "iso", y, phi, x) - U) < 1e-10 * abs(U)
+    # second order in the residual: perturb x by eps -> error ~ eps^2
+    g = np.random.default_rng(0).normal(size=len(y))
+    e1 = hmc.potential_at(X, th, "iso", y, phi, x + 1e-3 * g) - U
+    e2 = hmc.potential_at(X, th, "iso", y, phi, x + 2e-3 * g) - U
+    assert e1 < 0 and e2 < 0 and 3.5 < e2 / e1 < 4.5
+
+
+def test_leapfrog_reversible():
+    X, y, th, phi = _problem()
+    pi0 = np.array([0.3, -0.7, 0.2])
+    th1, pi1 = hmc.leapfrog(X, "iso", y, phi, th, pi0, 0.05, 6)
+    th2, pi2 = hmc.leapfrog(X, "iso", y, phi, th1, -pi1, 0.05, 6)
+    np.testing.assert_allclose(th2, th, atol=1e-11)
+    np.testing.assert_allclose(-pi2, pi0, atol=1e-11)
+
+
+def test_leapfrog_second_order_energy_error():
+    X, y, th, phi = _problem()
+    pi0 = np.array([0.5, -0.4, 0.3])
+    T = 0.4
+    errs = []
+    for n in (4, 8, 16):
+        th1, pi1 = hmc.leapfrog(X, "iso", y, phi, th, pi0, T / n, n)
+        errs.append(abs(hmc.hamiltonian(X, th1, "iso", y, phi, pi1) - hmc.hamiltonian(X, th, "iso", y, phi, pi0)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, errs
+
+
+def test_leapfrog_one_step_matches_definition():
+    # one DKD step written out: theta_1/2 = theta + dt/2 pi; pi' = pi - dt F(theta_1/2);
+    # theta' = theta_1/2 + dt/2 pi'.  The force is taken from finite differences of U so this
+    # does not reuse the oracle's force routine.
+    X, y, th, phi = _problem()
+    pi0 = np.array([0.2, 0.1, -0.3])
+    dt = 0.1
+    th_h = th + 0.5 * dt * pi0
+    h = 1e-6
+    F = np.array([(hmc.potential(X, th_h + h * e, "iso", y, phi) - hmc.potential(X, th_h - h * e, "iso", y, phi)) / (2 * h)
+                  for e in np.eye(3)])
+    pi1 = pi0 - dt * F
+    th1 = th_h + 0.5 * dt * pi1
+    a, b = hmc.leapfrog(X, "iso", y, phi, th, pi0, dt, 1)
+    np.testing.assert_allclose(a, th1, atol=1e-8)
+    np.testing.assert_allclose(b, pi1, atol=1e-8)
+
+
+def test_leapfrog_volume_preserving():
+    X, y, th, phi = _problem(n=12)
+    z0 = np.concatenate([th, [0.2, -0.1, 0.4]])
+
+    def flow(z):
+        a, b = hmc.leapfrog(X, "iso", y, phi, z[:3], z[3:], 0.1, 3)
+        return np.concatenate([a, b])
+
+    h = 1e-6
+    J = np.stack([(flow(z0 + h * e) - flow(z0 - h * e)) / (2 * h) for e in np.eye(6)], axis=1)
+    assert abs(np.linalg.det(J) - 1.0) < 1e-6
+
+
+def test_accept_rule():
+    assert hmc.accept(5.0, 5.0, 0.999)
+    assert hmc.accept(5.0, 6.0, math.exp(-1.0) - 1e-12)
+    assert not hmc.accept(5.0, 6.0, math.exp(-1.0) + 1e-9)
+    assert hmc.accept(0.0, 100.0, 0.0)
+
+
+def test_trajectory_reject_restores():
+    X, y, th, phi = _problem()
+    pi0 = np.array([3.0, 3.0, 3.0])
+    r = hmc.trajectory(X, "iso", y, phi, th, pi0, 0.5, 5, u=1.0 - 1e-15)
+    if r["H1"] > r["H0"]:
+        assert not r["accepted"]
+        np.testing.assert_array_equal(r["theta"], th)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_gaussian_integral_identity(n):
+    g = np.random.default_rng(n)
+    B = g.normal(size=(n, n))
+    A = B @ B.T + 0.5 * np.eye(n)
+    val = posterior.gaussian_integral(A, n_nodes={1: 401, 2: 201, 3: 121}[n])
+    assert abs(val - np.linalg.det(A) ** -0.5) < 1e-10 * np.linalg.det(A) ** -0.5
+
+
+def test_phi_marginal_is_posterior():
+    # Integrating the extended density over phi gives P(theta) up to a theta-independent
+    # constant (N/2) log(2 pi), checked across a theta grid at N = 2.
+    X = np.array([[0.1], [0.55]])
+    y = np.array([0.3, -0.8])
+    diffs = []
+    for la in (-1.0, 0.0, 0.7):
+        for ll in (-1.5, -0.5, 0.4):
+            th = np.array([la, ll, np.log(0.2)])
+            diffs.append(posterior.log_phi_marginal(X, th, "iso", y, n_nodes=201) - posterior.log_posterior(X, th, "iso", y))
+    np.testing.assert_allclose(diffs, math.log(2 * math.pi), atol=1e-10)
+
+
+def test_log_posterior_two_points_closed_form():
+    X = np.array([[0.0], [1.0]])
+    y = np.array([1.0, 0.5])
+    a, l, s2 = 1.5, 0.8, 0.1
+    off = a * math.exp(-1.0 / (2 * l * l))
+    A = np.array([[a + s2, off], [off, a + s2]])
+    det = (a + s2) ** 2 - off ** 2
+    quad = ((a + s2) * (y[0] ** 2 + y[1] ** 2) - 2 * off * y[0] * y[1]) / det
+    expect = -0.5 * math.log(det) - 0.5 * quad
+    assert abs(posterior.log_posterior(X, np.log([a, l, s2]), "iso", y) - expect) < 1e-13
