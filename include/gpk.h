@@ -1,0 +1,206 @@
+/*
+ * gpk.h -- C ABI of libgpk: matrix-free kernel-matrix products, quadratic-form gradients and
+ * HMC leapfrog trajectories for determinant-free fully Bayesian Gaussian process regression,
+ * on hand-written gfx950 (MI355X) kernels.
+ *
+ * Notation (Kielstra & Lindsey, "A gradient-based and determinant-free framework for fully
+ * Bayesian Gaussian process regression"):
+ *   A(theta) = sigma^2 I + K(theta)          Section 2, eq. (kerdef); K is eq. (kernmat)
+ *   K_ij = alpha exp(-1/2 sum_k (x_ik - x_jk)^2 / l_k^2)
+ *                                            squared-exponential kernel of Section 1; one
+ *                                            length-scale (GP_SE_ISO) or one per coordinate
+ *                                            (GP_SE_ARD)
+ *   theta = (log alpha, log l_1 .. log l_L, log sigma^2), natural logs, L = 1 (ISO) or d (ARD),
+ *   n_theta = L + 2.  In this library "K_theta" always means the full A(theta) unless
+ *   GP_NO_NOISE is set.
+ *
+ * Conventions common to every entry point
+ *   - Ownership: every array argument is caller-owned memory; the library never allocates,
+ *     frees or retains caller memory.  Arrays marked "device" must be device memory of the
+ *     current HIP device; arrays marked "host" are read during the call only.
+ *   - Asynchrony: work is enqueued on `stream` (0 = the null stream); results are valid once
+ *     the stream has been synchronised.  The call returns after enqueueing.
+ *   - Validation: every argument error is detected on the host before anything is enqueued;
+ *     the call then returns a nonzero status with no side effect and gp_last_error() describes
+ *     it.  GP_ERR_HIP reports a failed HIP launch or runtime call.
+ *   - Layout: matrices are row-major with a leading dimension (elements between consecutive
+ *     rows); point sets X are N x d row-major with leading dimension d.
+ *   - Precision (gp_kernel.prec): GP_F64 -> all real arrays are double; GP_F32 -> X, V, U, out
+ *     are float (parameters, weights, gradients, quadratic forms and energies stay double);
+ *     GP_BF16X -> as GP_F32 in memory, but the coordinate cross term is formed from bfloat16
+ *     hi/lo splits on the matrix cores with float accumulation.
+ *   - Determinism: no floating-point atomics; for a fixed (n, r, d, precision) the summation
+ *     order is fixed, so repeated calls give bitwise-identical results.
+ *   - Thread safety: calls on distinct streams with distinct workspaces may run concurrently.
+ *   - Workspace: `ws` is device scratch of at least the size the matching *_workspace_size
+ *     function returns (0 bytes allowed when that size is 0); its contents on entry are
+ *     irrelevant.
+ */
+#ifndef GPK_H
+#define GPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gp_status;
+enum {
+  GP_OK = 0,
+  GP_ERR_ARG = 1,         /* null pointer, bad enum, aliasing, bad parameter value */
+  GP_ERR_SHAPE = 2,       /* n, r, d or a leading dimension out of range */
+  GP_ERR_UNSUPPORTED = 3, /* valid but not implemented combination */
+  GP_ERR_WORKSPACE = 4,   /* ws missing or smaller than the required size */
+  GP_ERR_HIP = 5          /* a HIP launch or runtime call failed */
+};
+
+enum { GP_SE_ISO = 0, GP_SE_ARD = 1 };
+enum { GP_F64 = 0, GP_F32 = 1, GP_BF16X = 2 };
+enum { GP_NO_NOISE = 1 /* apply K(theta) (eq. kernmat) instead of A(theta) */ };
+
+/* Kernel description.  d: 1..64 coordinates. */
+typedef struct {
+  int32_t kind;  /* GP_SE_ISO or GP_SE_ARD */
+  int32_t prec;  /* GP_F64, GP_F32 or GP_BF16X */
+  int32_t d;     /* spatial dimension */
+  int32_t flags; /* 0 or GP_NO_NOISE */
+} gp_kernel;
+
+/* Per-chain status bits written by gp_hmc_leapfrog; any set bit forces a reject. */
+enum {
+  GP_CHAIN_CG_MAXIT = 1,        /* a linear solve hit cg_maxit before reaching cg_tol */
+  GP_CHAIN_NONFINITE_H = 2,     /* an energy was NaN or infinite */
+  GP_CHAIN_NONFINITE_THETA = 4  /* theta or pi became NaN or infinite */
+};
+
+/* Message of the last failed call on the calling thread ("" if none).  Valid until the next
+ * gp_* call on the same thread. */
+const char *gp_last_error(void);
+/* Static name of a status code. */
+const char *gp_status_string(gp_status s);
+/* n_theta for a kernel description, or -1 if it is invalid. */
+int32_t gp_n_theta(const gp_kernel *k);
+
+/* Bytes of workspace that gp_kmatvec and gp_quadform_grad need for n points and r columns.
+ * Returns 0 for an invalid description. */
+size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r);
+
+/*
+ * gp_kmatvec -- out = (A(theta) + diag(col_shift)) V, column by column, matrix-free.
+ *
+ * The matrix-free product with A(theta) of eq. (kerdef) (or K of eq. (kernmat) with
+ * GP_NO_NOISE): entries are recomputed on the fly, memory stays O(N (d + r)).  Section 2 and the
+ * discussion of matrix-free primitives in Section 1; each conjugate-gradient iteration of the
+ * solves in Section 3.2.1 (eq. xtheta) and of the shifted solves of the pole expansion
+ * (Section 3.1, eq. pex) is one such product.
+ *
+ *   X        device, n x d, leading dimension d
+ *   theta    device double[n_theta]; read on the device, so a captured graph sees updates
+ *   r        number of right-hand sides, r >= 0 (r = 0 or n = 0: nothing is done)
+ *   V        device, n x r, leading dimension ldv >= r
+ *   col_shift device double[r]: lambda_c added to the diagonal for column c, or NULL (= 0)
+ *   out      device, n x r, leading dimension ldo >= r; must not overlap V
+ */
+gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                     int32_t r, const void *V, int64_t ldv, const double *col_shift,
+                     void *out, int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * gp_quadform_grad -- Q = sum_c w_c u_c^T A(theta) v_c, its theta-gradient and A U, A V in one
+ * pass over the pairs.
+ *
+ * The force of Section 3.2.1 needs only solves and the theta-gradient of quadratic forms in
+ * A(theta) (capacity (3)); with U = V = [x | phi] and w = (-1/2, +1/2) the gradient is the force
+ * of eq. (u) at x frozen.  The derivatives are
+ *   dQ/dlog alpha   = sum_ij K_ij S_ij,        S_ij = sum_c w_c u_ic v_jc
+ *   dQ/dlog l_k     = sum_ij K_ij (x_ik - x_jk)^2 / l_k^2 S_ij   (ISO: r_ij^2 / l^2)
+ *   dQ/dlog sigma^2 = sigma^2 sum_c w_c u_c . v_c
+ * Kernel entries are recomputed, never stored.  GP_NO_NOISE is not accepted here.
+ *
+ *   U, V       device, n x r (r in 1..32), leading dimensions ldu, ldv >= r; U may equal V
+ *   w          device double[r] weights, or NULL (all 1)
+ *   grad_theta device double[n_theta] (dQ/dtheta), or NULL
+ *   quad       device double[r], q_c = u_c^T A v_c (unweighted), or NULL
+ *   AU, AV     device, n x r, leading dimensions ldau, ldav >= r, or NULL; A U is dQ/dv per
+ *              column up to w_c, A V is dQ/du.  They must not overlap U or V or each other.
+ * At least one output must be non-NULL.
+ */
+gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                           int32_t r, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                           const double *w, double *grad_theta, double *quad, void *AU,
+                           int64_t ldau, void *AV, int64_t ldav, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Trajectory parameters. */
+typedef struct {
+  int32_t n_steps;  /* leapfrog steps per trajectory, N_int >= 0 */
+  double dt;        /* step size */
+  double cg_tol;    /* relative residual |y - A x|_2 / |y|_2 at which CG stops, > 0 */
+  int32_t cg_maxit; /* CG iteration limit per solve, >= 1 */
+  int32_t mode;     /* GP_HMC_PLAIN, GP_HMC_BATCHED or GP_HMC_GRAPH */
+} gp_hmc_params;
+
+enum {
+  GP_HMC_PLAIN = 0,   /* one chain at a time, one kernel per operation, host-checked CG */
+  GP_HMC_BATCHED = 1, /* every chain of every instance in one persistent launch */
+  GP_HMC_GRAPH = 2    /* as GP_HMC_BATCHED, launched by replaying a captured hipGraph */
+};
+
+/* A batch of independent GPR instances, each with `chains_per_inst` chains.  Instance b has
+ * n_points[b] points of dimension d[b] (or k->d if d is NULL).  Packing (all host arrays):
+ *   X      element offset x_offsets[b] (or offsets[b] * d_b if x_offsets is NULL), n_b x d_b
+ *   y      row offset offsets[b]
+ *   phi, x_warm  chain h of instance b at  chains_per_inst * offsets[b] + h * n_b
+ *   theta, pi    chain h of instance b at  chains_per_inst * tofs_b + h * n_theta_b, where
+ *                tofs_b = sum of n_theta over instances before b
+ *   per-chain scalars  index b * chains_per_inst + h
+ * The row ranges [offsets[b], offsets[b] + n_b) must not overlap. */
+typedef struct {
+  int32_t n_inst;
+  int32_t chains_per_inst;
+  const int64_t *n_points;  /* host [n_inst], each >= 1 */
+  const int64_t *offsets;   /* host [n_inst] */
+  const int32_t *d;         /* host [n_inst] or NULL */
+  const int64_t *x_offsets; /* host [n_inst] or NULL */
+} gp_batch;
+
+/* Bytes of workspace gp_hmc_leapfrog needs; 0 for an invalid description. */
+size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b);
+
+/*
+ * gp_hmc_leapfrog -- one HMC trajectory of theta given phi for every chain: the Hamiltonian
+ * H = U_phi(theta) + 1/2 pi^T pi (Section 3.2, eq. U, M = I), n_steps drift-kick-drift
+ * Stormer-Verlet steps (Section 3.2.2) with the force of Section 3.2.1 (solve A x = y by
+ * conjugate gradients warm-started from x_warm, then the frozen-x gradient of eq. (u) as one
+ * quadratic-form pass), and the Metropolis decision of Algorithm 1 (steps 6-10).
+ *
+ * The energy uses the variational form y^T A^{-1} y ~ 2 y^T x - x^T A x of the solved x.
+ * Randomness is supplied by the caller: pi already drawn, u_accept uniform on [0, 1).
+ *
+ *   X, y        device, packed per gp_batch; X in the kernel precision, y likewise
+ *   phi         device, per chain, kernel precision
+ *   theta, pi   device double, in/out: on return theta is the accepted state (the start state
+ *               if rejected) and pi the proposal's end momentum (start momentum if rejected)
+ *   x_warm      device, in/out, kernel precision: CG start at theta on entry; on return the
+ *               solve at the returned theta
+ *   u_accept    device double per chain, or NULL: no decision, every proposal is kept
+ *   H0, H1      device double per chain: energies at the start and at the proposal
+ *   accepted    device int32 per chain (1 accepted, 0 rejected)
+ *   status      device int32 per chain, GP_CHAIN_* bits
+ *   cg_iters    device int32 per chain: CG iterations used over the trajectory, or NULL
+ */
+gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
+                          const void *X, const void *y, const void *phi, double *theta,
+                          double *pi, void *x_warm, const double *u_accept, double *H0,
+                          double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPK_H */

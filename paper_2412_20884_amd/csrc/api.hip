@@ -1,0 +1,327 @@
+// C ABI of libgpk: argument validation, workspace sizing and dispatch of the product kernels.
+// Every argument check happens before the first HIP call of an entry point.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gpk.h"
+#include "pass.h"
+
+namespace gpk {
+
+static thread_local char g_err[512];
+
+gp_status fail(gp_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+gp_status hip_fail(hipError_t e, const char *where) {
+  return fail(GP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Final fixed-order sum of the per-block records.  One thread per record entry.
+__global__ void reduce_records(const double *rp, int64_t np, const double *rf, int64_t nf,
+                               int nrec, int nth, int L, double *grad, double *quad) {
+  const int e = threadIdx.x;
+  if (e >= nrec) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < np; ++b) s += rp[b * nrec + e];
+  for (int64_t b = 0; b < nf; ++b) s += rf[b * nrec + e];
+  if (e < nth) {
+    const double f = (e >= 1 && e <= L) ? 2.0 * kLn2 : 1.0;
+    if (grad) grad[e] = s * f;
+  } else if (quad) {
+    quad[e - nth] = s;
+  }
+}
+
+__global__ void fill_zero(double *a, int64_t m) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) a[e] = 0.0;
+}
+
+hipError_t zero_doubles(double *a, int64_t m, hipStream_t s) {
+  if (!a || m <= 0) return hipSuccess;
+  fill_zero<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(a, m);
+  return hipGetLastError();
+}
+
+int64_t pair_blocks(const PassDesc &p) {
+  const int rows = p.use_mfma ? kRowsMfma : kRowsValu;
+  return ((p.n + rows - 1) / rows) * p.splits;
+}
+
+int64_t fin_blocks(const PassDesc &p) {
+  return p.splits > 1 ? (p.n + kThreads - 1) / kThreads : 0;
+}
+
+hipError_t launch_stage(int prec, const void *X, int64_t n, int d, int dp, int kind,
+                        const double *theta, char *ws, const WsLayout &L, hipStream_t s) {
+  if (prec == kF64) return launch_stage_f64(X, n, d, dp, kind, theta, ws, L, s);
+  return launch_stage_f32(X, n, d, dp, kind, theta, ws, L, s);
+}
+
+hipError_t launch_pass(const PassDesc &p, hipStream_t s) {
+  if (p.use_mfma) return launch_pass_mfma(p, s);
+  if (p.prec == kF64) return launch_pass_f64(p, s);
+  return launch_pass_f32(p, s);
+}
+
+hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s) {
+  if (!grad && !quad) return hipSuccess;
+  reduce_records<<<1, 128, 0, s>>>(p.rec_pair, pair_blocks(p), p.rec_fin, fin_blocks(p),
+                                   p.nrec, p.nth, p.kind == 0 ? 1 : p.d, grad, quad);
+  return hipGetLastError();
+}
+
+// ---- shared validation ------------------------------------------------------------------
+
+static gp_status check_kernel(const gp_kernel *k, bool allow_no_noise) {
+  if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
+  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD)
+    return fail(GP_ERR_ARG, "kernel kind %d is not GP_SE_ISO or GP_SE_ARD", k->kind);
+  if (k->prec != GP_F64 && k->prec != GP_F32 && k->prec != GP_BF16X)
+    return fail(GP_ERR_ARG, "precision %d is not GP_F64, GP_F32 or GP_BF16X", k->prec);
+  if (k->d < 1 || k->d > kMaxD) return fail(GP_ERR_SHAPE, "d = %d outside 1..%d", k->d, kMaxD);
+  if (k->flags & ~GP_NO_NOISE) return fail(GP_ERR_ARG, "unknown flag bits 0x%x", k->flags);
+  if (!allow_no_noise && (k->flags & GP_NO_NOISE))
+    return fail(GP_ERR_ARG, "GP_NO_NOISE is not accepted by this entry point");
+  return GP_OK;
+}
+
+static int nth_of(const gp_kernel *k) { return k->kind == GP_SE_ISO ? 3 : k->d + 2; }
+
+static size_t elem_size(int prec) { return prec == GP_F64 ? sizeof(double) : sizeof(float); }
+
+static bool overlap(const void *a, int64_t rows_a, int64_t ld_a, int cols_a, const void *b,
+                    int64_t rows_b, int64_t ld_b, int cols_b, size_t es) {
+  if (!a || !b) return false;
+  const char *a0 = (const char *)a, *b0 = (const char *)b;
+  const char *a1 = a0 + ((rows_a - 1) * ld_a + cols_a) * (int64_t)es;
+  const char *b1 = b0 + ((rows_b - 1) * ld_b + cols_b) * (int64_t)es;
+  return a0 < b1 && b0 < a1;
+}
+
+struct Plan {
+  int dp;
+  int rpass;
+  int splits;
+  int use_mfma;
+  int nrec;
+  WsLayout L;
+};
+
+static Plan make_plan(const gp_kernel *k, int64_t n, int r) {
+  Plan pl;
+  pl.dp = padded_dim(k->d);
+  pl.rpass = r < kMaxRPass ? r : kMaxRPass;
+  if (pl.rpass < 1) pl.rpass = 1;
+  pl.use_mfma = mfma_supported(k->prec, k->kind, k->d, pl.rpass) ? 1 : 0;
+  const int rows = pl.use_mfma ? kRowsMfma : kRowsValu;
+  pl.splits = choose_splits(n, rows);
+  pl.nrec = nth_of(k) + pl.rpass;
+  const int64_t pb = ((n + rows - 1) / rows) * pl.splits;
+  const int64_t fb = pl.splits > 1 ? (n + kThreads - 1) / kThreads : 0;
+  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.splits, pb, fb, pl.nrec,
+                   pl.use_mfma ? mfma_scratch_bytes() : 0);
+  return pl;
+}
+
+static PassDesc base_desc(const gp_kernel *k, const Plan &pl, int64_t n, const double *theta,
+                          char *ws) {
+  PassDesc p;
+  memset(&p, 0, sizeof(p));
+  p.prec = k->prec == GP_F64 ? kF64 : kF32;
+  p.kind = k->kind;
+  p.d = k->d;
+  p.dp = pl.dp;
+  p.n = n;
+  p.xs = ws + pl.L.xs;
+  p.theta = theta;
+  p.splits = pl.splits;
+  p.outp = (double *)(ws + pl.L.outp);
+  p.rec_pair = (double *)(ws + pl.L.rec_pair);
+  p.rec_fin = (double *)(ws + pl.L.rec_fin);
+  p.nth = nth_of(k);
+  p.use_mfma = pl.use_mfma;
+  p.mfma_scratch = ws + pl.L.scratch;
+  return p;
+}
+
+}  // namespace gpk
+
+using namespace gpk;
+
+extern "C" {
+
+const char *gp_last_error(void) { return g_err; }
+
+const char *gp_status_string(gp_status s) {
+  switch (s) {
+    case GP_OK: return "GP_OK";
+    case GP_ERR_ARG: return "GP_ERR_ARG";
+    case GP_ERR_SHAPE: return "GP_ERR_SHAPE";
+    case GP_ERR_UNSUPPORTED: return "GP_ERR_UNSUPPORTED";
+    case GP_ERR_WORKSPACE: return "GP_ERR_WORKSPACE";
+    case GP_ERR_HIP: return "GP_ERR_HIP";
+    default: return "GP_UNKNOWN_STATUS";
+  }
+}
+
+int32_t gp_n_theta(const gp_kernel *k) {
+  if (check_kernel(k, true) != GP_OK) return -1;
+  return nth_of(k);
+}
+
+size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
+  if (check_kernel(k, true) != GP_OK || n < 0 || r < 0) return 0;
+  if (n == 0 || r == 0) return 0;
+  if (k->prec == GP_BF16X) return 0;
+  return make_plan(k, n, r).L.total;
+}
+
+gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                     int32_t r, const void *V, int64_t ldv, const double *col_shift, void *out,
+                     int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  gp_status st = check_kernel(k, true);
+  if (st) return st;
+  if (k->prec == GP_BF16X)
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X products are not available in this build");
+  if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
+  if (r < 0) return fail(GP_ERR_SHAPE, "r = %d < 0", r);
+  if (n == 0 || r == 0) return GP_OK;
+  if (!X || !theta || !V || !out) return fail(GP_ERR_ARG, "X, theta, V and out must be non-NULL");
+  if (ldv < r || ldo < r)
+    return fail(GP_ERR_SHAPE, "leading dimensions ldv=%lld ldo=%lld must be >= r=%d",
+                (long long)ldv, (long long)ldo, r);
+  const size_t es = elem_size(k->prec);
+  if (overlap(V, n, ldv, r, out, n, ldo, r, es)) return fail(GP_ERR_ARG, "out overlaps V");
+  const Plan pl = make_plan(k, n, r);
+  if (!ws || ws_bytes < pl.L.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
+                ws ? ws_bytes : (size_t)0);
+  char *w = (char *)ws;
+  hipError_t e = launch_stage(k->prec == GP_F64 ? kF64 : kF32, X, n, k->d, pl.dp, k->kind, theta,
+                              w, pl.L, stream);
+  if (e != hipSuccess) return hip_fail(e, "stage");
+  for (int c0 = 0; c0 < r; c0 += pl.rpass) {
+    const int rc = r - c0 < pl.rpass ? r - c0 : pl.rpass;
+    PassDesc p = base_desc(k, pl, n, theta, w);
+    p.R = rc;
+    p.nrec = nth_of(k) + rc;
+    // a narrow trailing chunk runs on the VALU kernel (same rows per block and split count)
+    p.use_mfma = mfma_supported(k->prec, k->kind, k->d, rc) ? pl.use_mfma : 0;
+    p.Y = (const char *)V + c0 * es;
+    p.ldy = ldv;
+    p.col_shift = col_shift ? col_shift + c0 : nullptr;
+    p.no_noise = (k->flags & GP_NO_NOISE) ? 1 : 0;
+    p.out = (char *)out + c0 * es;
+    p.ldo = ldo;
+    e = launch_pass(p, stream);
+    if (e != hipSuccess) return hip_fail(e, "kmatvec pass");
+  }
+  return GP_OK;
+}
+
+gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                           int32_t r, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                           const double *w, double *grad_theta, double *quad, void *AU,
+                           int64_t ldau, void *AV, int64_t ldav, void *ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  clear_error();
+  gp_status st = check_kernel(k, false);
+  if (st) return st;
+  if (k->prec == GP_BF16X)
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X products are not available in this build");
+  if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
+  if (r < 1 || r > kMaxRPass) return fail(GP_ERR_SHAPE, "r = %d outside 1..%d", r, kMaxRPass);
+  if (!grad_theta && !quad && !AU && !AV)
+    return fail(GP_ERR_ARG, "at least one of grad_theta, quad, AU, AV must be non-NULL");
+  if (n == 0) {
+    // empty point set: Q = 0 and its gradient is 0
+    hipError_t e = zero_doubles(grad_theta, nth_of(k), stream);
+    if (e == hipSuccess) e = zero_doubles(quad, r, stream);
+    if (e != hipSuccess) return hip_fail(e, "zero fill");
+    return GP_OK;
+  }
+  if (!X || !theta || !U || !V) return fail(GP_ERR_ARG, "X, theta, U and V must be non-NULL");
+  if (ldu < r || ldv < r || (AU && ldau < r) || (AV && ldav < r))
+    return fail(GP_ERR_SHAPE, "a leading dimension is smaller than r=%d", r);
+  const size_t es = elem_size(k->prec);
+  const bool sym = (U == V && ldu == ldv);
+  if (overlap(AU, n, ldau, r, U, n, ldu, r, es) || overlap(AU, n, ldau, r, V, n, ldv, r, es) ||
+      overlap(AV, n, ldav, r, U, n, ldu, r, es) || overlap(AV, n, ldav, r, V, n, ldv, r, es) ||
+      overlap(AU, n, ldau, r, AV, n, ldav, r, es))
+    return fail(GP_ERR_ARG, "an output overlaps an input or the other output");
+  const Plan pl = make_plan(k, n, r);
+  if (!ws || ws_bytes < pl.L.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
+                ws ? ws_bytes : (size_t)0);
+  char *wsp = (char *)ws;
+  hipError_t e = launch_stage(k->prec == GP_F64 ? kF64 : kF32, X, n, k->d, pl.dp, k->kind,
+                              theta, wsp, pl.L, stream);
+  if (e != hipSuccess) return hip_fail(e, "stage");
+
+  // Pass 1: gradient, q_c and one of the products.  Y is the operand whose product is wanted;
+  // D is the other operand, so q_c = sum_i D_ic (A Y)_ic = u_c^T A v_c either way.
+  PassDesc p = base_desc(k, pl, n, theta, wsp);
+  p.R = r;
+  p.nrec = nth_of(k) + r;
+  p.P = U;
+  p.ldp = ldu;
+  p.Q = V;
+  p.ldq = ldv;
+  p.w = w;
+  if (sym) {
+    p.Y = U;
+    p.ldy = ldu;
+    p.D = U;
+    p.ldd = ldu;
+    p.out = AU ? AU : AV;
+    p.ldo = AU ? ldau : ldav;
+  } else if (AV && !AU) {
+    p.Y = V;
+    p.ldy = ldv;
+    p.D = U;
+    p.ldd = ldu;
+    p.out = AV;
+    p.ldo = ldav;
+  } else {
+    p.Y = U;
+    p.ldy = ldu;
+    p.D = V;
+    p.ldd = ldv;
+    p.out = AU;
+    p.ldo = ldau;
+  }
+  e = launch_pass(p, stream);
+  if (e != hipSuccess) return hip_fail(e, "quadform pass");
+  e = launch_reduce(p, grad_theta, quad, stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  if (sym && AU && AV) {
+    e = hipMemcpy2DAsync(AV, ldav * es, AU, ldau * es, r * es, n, hipMemcpyDeviceToDevice,
+                         stream);
+    if (e != hipSuccess) return hip_fail(e, "copy AU -> AV");
+  } else if (!sym && AU && AV) {
+    // Pass 2: the second product without gradient sums.
+    PassDesc q = base_desc(k, pl, n, theta, wsp);
+    q.R = r;
+    q.nrec = nth_of(k) + r;
+    q.Y = V;
+    q.ldy = ldv;
+    q.out = AV;
+    q.ldo = ldav;
+    e = launch_pass(q, stream);
+    if (e != hipSuccess) return hip_fail(e, "quadform second product");
+  }
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+"""ctypes binding of libgpk (include/gpk.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; this module checks tensor placement,
+dtype and layout, allocates the workspace and output tensors with PyTorch (device memory and
+streams are the only things PyTorch provides here) and calls the C entry points on the current
+stream.  The library is loaded on first use; if it has not been built the call fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgpk.so")
+
+ISO, ARD = 0, 1
+F64, F32, BF16X = 0, 1, 2
+NO_NOISE = 1
+PLAIN, BATCHED, GRAPH = 0, 1, 2
+CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA = 1, 2, 4
+
+EXPORTED = (
+    "gp_last_error", "gp_status_string", "gp_n_theta", "gp_workspace_size", "gp_kmatvec",
+    "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog",
+)
+
+
+class GpkError(RuntimeError):
+    def __init__(self, status, name, message):
+        super().__init__(f"{name}: {message}")
+        self.status = status
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("prec", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class HmcParams(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("dt", ctypes.c_double), ("cg_tol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("chains_per_inst", ctypes.c_int32),
+                ("n_points", ctypes.POINTER(ctypes.c_int64)), ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("d", ctypes.POINTER(ctypes.c_int32)), ("x_offsets", ctypes.POINTER(ctypes.c_int64))]
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+
+
+def lib():
+    """The loaded libgpk (loads it on first call; raises if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python -m paper_2412_20884_amd.csrc.build")
+    L = ctypes.CDLL(LIB_PATH)
+    L.gp_last_error.restype = ctypes.c_char_p
+    L.gp_last_error.argtypes = []
+    L.gp_status_string.restype = ctypes.c_char_p
+    L.gp_status_string.argtypes = [_i32]
+    L.gp_n_theta.restype = _i32
+    L.gp_n_theta.argtypes = [ctypes.POINTER(Kernel)]
+    L.gp_workspace_size.restype = _sz
+    L.gp_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32]
+    L.gp_kmatvec.restype = _i32
+    L.gp_kmatvec.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp, _vp,
+                             _i64, _vp, _sz, _vp]
+    L.gp_quadform_grad.restype = _i32
+    L.gp_quadform_grad.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp,
+                                   _i64, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp]
+    L.gp_hmc_workspace_size.restype = _sz
+    L.gp_hmc_workspace_size.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
+                                        ctypes.POINTER(Batch)]
+    L.gp_hmc_leapfrog.restype = _i32
+    L.gp_hmc_leapfrog.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
+                                  ctypes.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    _LIB = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        L = lib()
+        raise GpkError(status, L.gp_status_string(status).decode(), L.gp_last_error().decode())
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def kind_code(kind):
+    if kind in (ISO, "iso"):
+        return ISO
+    if kind in (ARD, "ard"):
+        return ARD
+    raise ValueError(f"unknown kernel kind {kind!r}")
+
+
+def prec_code(dtype, prec=None):
+    if prec in ("bf16x", BF16X):
+        if dtype != torch.float32:
+            raise TypeError("bf16x takes float32 tensors")
+        return BF16X
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def make_kernel(kind, X, prec=None, no_noise=False):
+    return Kernel(kind_code(kind), prec_code(X.dtype, prec), X.shape[1], NO_NOISE if no_noise else 0)
+
+
+def n_theta(kind, d):
+    return 3 if kind_code(kind) == ISO else d + 2
+
+
+def _rowmajor(t, name):
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
+
+
+def _same(device, dtype, **ts):
+    for name, t in ts.items():
+        if t is None:
+            continue
+        if t.device != device:
+            raise ValueError(f"{name} is on {t.device}, expected {device}")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+
+
+def workspace_size(kernel, n, r):
+    return int(lib().gp_workspace_size(ctypes.byref(kernel), int(n), int(r)))
+
+
+def _workspace(nbytes, device, ws=None):
+    if nbytes == 0:
+        return None
+    if ws is not None and ws.numel() >= nbytes:
+        return ws
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, out=None, ws=None):
+    """(A(theta) + diag(col_shift)) V through gp_kmatvec.  V may be 1-D (one column)."""
+    squeeze = V.dim() == 1
+    V2 = V[:, None] if squeeze else V
+    _rowmajor(X, "X")
+    _rowmajor(V2, "V")
+    if X.stride(0) != X.shape[1]:
+        raise ValueError("X must be contiguous")
+    dev = X.device
+    _same(dev, X.dtype, V=V2)
+    _same(dev, torch.float64, theta=theta, col_shift=col_shift)
+    k = make_kernel(kind, X, prec, no_noise)
+    n, r = X.shape[0], V2.shape[1]
+    if out is None:
+        out = torch.empty((n, r), dtype=X.dtype, device=dev)
+    out2 = out[:, None] if out.dim() == 1 else out
+    _rowmajor(out2, "out")
+    w = _workspace(workspace_size(k, n, r), dev, ws)
+    _check(lib().gp_kmatvec(ctypes.byref(k), n, _p(X), _p(theta), r, _p(V2), V2.stride(0),
+                            _p(col_shift), _p(out2), out2.stride(0), _p(w),
+                            0 if w is None else w.numel(), _stream(dev)))
+    return out2[:, 0] if squeeze else out
+
+
+def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=True,
+                  want_quad=True, want_AU=False, want_AV=False, ws=None):
+    """sum_c w_c u_c^T A v_c: dict with 'grad' (n_theta), 'quad' (R), 'AU', 'AV' as requested."""
+    if V is None:
+        V = U
+    _rowmajor(X, "X")
+    _rowmajor(U, "U")
+    _rowmajor(V, "V")
+    dev = X.device
+    _same(dev, X.dtype, U=U, V=V)
+    _same(dev, torch.float64, theta=theta, w=w)
+    k = make_kernel(kind, X, prec)
+    n, r = X.shape[0], U.shape[1]
+    nt = n_theta(kind, X.shape[1])
+    grad = torch.empty(nt, dtype=torch.float64, device=dev) if want_grad else None
+    quad = torch.empty(r, dtype=torch.float64, device=dev) if want_quad else None
+    AU = torch.empty((n, r), dtype=X.dtype, device=dev) if want_AU else None
+    AV = torch.empty((n, r), dtype=X.dtype, device=dev) if want_AV else None
+    wk = _workspace(workspace_size(k, n, r), dev, ws)
+    _check(lib().gp_quadform_grad(ctypes.byref(k), n, _p(X), _p(theta), r, _p(U), U.stride(0),
+                                  _p(V), V.stride(0), _p(w), _p(grad), _p(quad), _p(AU),
+                                  r, _p(AV), r, _p(wk), 0 if wk is None else wk.numel(),
+                                  _stream(dev)))
+    return {"grad": grad, "quad": quad, "AU": AU, "AV": AV}

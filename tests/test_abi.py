@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every symbol include/gpk.h declares, and rejects bad
+arguments on the host before touching a GPU (so these run on a CPU-only machine)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_20884_amd import gpk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpk.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(gpk.LIB_PATH), reason="libgpk.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert set(syms) == set(gpk.EXPORTED), syms
+    L = ctypes.CDLL(gpk.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_status_strings_and_n_theta():
+    L = gpk.lib()
+    assert L.gp_status_string(0) == b"GP_OK"
+    assert L.gp_status_string(4) == b"GP_ERR_WORKSPACE"
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 3, 0))) == 3
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 8, 0))) == 10
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(7, gpk.F32, 8, 0))) == -1
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 65, 0))) == -1
+
+
+def _kmv(k, n=10, X=1, th=1, r=2, V=4096, ldv=2, out=1 << 20, ldo=2, ws=8, wsb=1 << 30):
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+    return L.gp_kmatvec(k, n, vp(X), vp(th), r, vp(V), ldv, None, vp(out), ldo, vp(ws), wsb, None)
+
+
+def test_kmatvec_validation():
+    L = gpk.lib()
+    good = ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 3, 0))
+    assert _kmv(None) == 1
+    assert b"NULL" in L.gp_last_error()
+    assert _kmv(ctypes.byref(gpk.Kernel(5, gpk.F32, 3, 0))) == 1
+    assert _kmv(ctypes.byref(gpk.Kernel(gpk.ISO, 9, 3, 0))) == 1
+    assert _kmv(ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 0, 0))) == 2
+    assert _kmv(ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 3, 8))) == 1
+    assert _kmv(good, n=-1) == 2
+    assert _kmv(good, r=-1) == 2
+    assert _kmv(good, X=0) == 1
+    assert _kmv(good, ldv=1) == 2
+    assert _kmv(good, ldo=1) == 2
+    # out overlapping V
+    assert _kmv(good, V=4096, out=4100) == 1
+    # workspace missing / too small
+    assert _kmv(good, ws=0) == 4
+    assert _kmv(good, wsb=16) == 4
+    assert b"workspace" in L.gp_last_error()
+    # empty problems are a no-op and succeed without touching memory
+    assert _kmv(good, n=0, X=0, V=0, out=0, ws=0) == 0
+    assert _kmv(good, r=0, X=0, V=0, out=0, ws=0) == 0
+
+
+def test_quadform_validation():
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+    k = ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, 0))
+
+    def q(kk=k, n=10, r=2, U=4096, V=8192, grad=1, quad=0, AU=0, AV=0, ldau=2, wsb=1 << 30):
+        return L.gp_quadform_grad(kk, n, vp(1), vp(1), r, vp(U), 2, vp(V), 2, None, vp(grad),
+                                  vp(quad), vp(AU), ldau, vp(AV), 2, vp(16), wsb, None)
+
+    assert q(r=0) == 2
+    assert q(r=33) == 2
+    assert q(grad=0) == 1
+    assert q(kk=ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, gpk.NO_NOISE))) == 1
+    assert q(AU=4096 + 8) == 1          # AU overlaps U
+    assert q(AU=1 << 20, ldau=1) == 2
+    assert q(wsb=8) == 4
+
+
+def test_workspace_size_monotone():
+    L = gpk.lib()
+    k = ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 3, 0))
+    a = L.gp_workspace_size(k, 1000, 4)
+    b = L.gp_workspace_size(k, 100000, 4)
+    assert 0 < a < b
+    assert L.gp_workspace_size(k, 0, 4) == 0
+    assert L.gp_workspace_size(None, 10, 4) == 0
