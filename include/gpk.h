@@ -74,7 +74,8 @@ typedef struct {
 enum {
   GP_CHAIN_CG_MAXIT = 1,        /* a linear solve hit cg_maxit before reaching cg_tol */
   GP_CHAIN_NONFINITE_H = 2,     /* an energy was NaN or infinite */
-  GP_CHAIN_NONFINITE_THETA = 4  /* theta or pi became NaN or infinite */
+  GP_CHAIN_NONFINITE_THETA = 4, /* theta or pi became NaN or infinite */
+  GP_CHAIN_ABORTED = 8          /* the batched scheduler stopped before the chain finished */
 };
 
 /* Message of the last failed call on the calling thread ("" if none).  Valid until the next

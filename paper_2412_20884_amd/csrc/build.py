@@ -28,7 +28,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
 ]
 
-SOURCES = ["api.hip", "pair_valu_f32.hip", "pair_valu_f64.hip", "pair_mfma.hip", "hmc.hip"]
+SOURCES = ["api.hip", "pair_valu_f32.hip", "pair_valu_f64.hip", "pair_mfma.hip", "hmc.hip",
+           "hmc_f32.hip", "hmc_f64.hip"]
 
 
 def _compile(src):

@@ -1,0 +1,79 @@
+// Device-resident chain state of the HMC trajectories and the job/phase encoding shared by the
+// plain (host-scheduled) and batched (persistent work-queue) schedulers.
+#pragma once
+
+#include "common.h"
+#include "gpk.h"
+
+namespace gpk {
+
+// Jobs a chain can publish; every job is split into n_rb row blocks x n_cs column splits.
+enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3 };
+// Why the current solve + quadratic-form pass is being done.
+enum HmcCtxKind { kCtxEnergy0 = 0, kCtxForce = 1, kCtxEnergy1 = 2 };
+
+constexpr int kHmcRec = 72;        // doubles per tile record: [0..7] scalars, [8 + k] gradient
+constexpr int kHmcTile = 256;      // rows per tile (one per thread)
+constexpr int kHmcMaxTheta = kMaxD + 2;
+
+template <typename T>
+struct HmcChain {
+  // problem (caller memory)
+  const T *X;
+  const T *y;
+  const T *phi;
+  double *theta;
+  double *pi;
+  T *x;
+  const double *u;  // uniform for the accept test, or null
+  double *H0out, *H1out;
+  int32_t *acc_out, *status_out, *iters_out;
+  int64_t n;
+  int d, dp, kind, nth;
+  // workspace
+  T *xs;       // n x dp scaled coordinates
+  T *r, *p, *q, *x0;
+  T *Z;        // n x 2: [x | phi]
+  double *qpart;  // n_cs x n partial products (n_cs > 1 only)
+  double *rec;    // n_jobs x kHmcRec
+  double theta0[kHmcMaxTheta], pi0[kHmcMaxTheta], F[kHmcMaxTheta];
+  double centre[kMaxD];
+  // schedule
+  int n_rb, n_cs, n_jobs;
+  int64_t col_chunk;
+  // state
+  int job;       // job being run by the tiles
+  int ctx;       // HmcCtxKind
+  int step;      // leapfrog step index
+  int it;        // CG iterations in the current solve
+  int cg_total;  // CG iterations over the trajectory
+  int status;
+  int done;
+  int jobs_run;  // jobs completed in this trajectory (bounded, see HmcRunParams::max_jobs)
+  double rr, yy, H0, H1;
+};
+
+struct HmcRunParams {
+  int n_steps;
+  double dt;
+  double tol2;  // cg_tol^2
+  int cg_maxit;
+  int max_jobs;  // (n_steps + 2) * (cg_maxit + 2) + 4: no trajectory can need more jobs
+};
+
+// Scheduling words of the batched launch, one per chain: (generation << 32) | claimed tiles.
+// Sizes of the kernel launches' static shared memory, shared by every tile variant.
+template <typename T>
+constexpr size_t hmc_tile_smem() {
+  return sizeof(T) * 64 * (kMaxD + 2) + 64;
+}
+
+struct HmcQueue {
+  unsigned long long *word;
+  unsigned int *finished;    // per chain: tiles finished in the current generation
+  unsigned int *chains_done;
+  unsigned int *abort;
+  unsigned int *order;       // chain indices, largest problems first
+};
+
+}  // namespace gpk

@@ -1,16 +1,226 @@
-// HMC leapfrog trajectories (placeholder until the CG/leapfrog kernels land).
+// gp_hmc_leapfrog host side: validation, workspace layout, per-chain descriptors and the three
+// schedulers (plain per-op launches, one persistent launch, a captured graph of it).
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
 #include "gpk.h"
-#include "pass.h"
+#include "hmc.h"
 
 namespace gpk {
+
 gp_status fail(gp_status st, const char *fmt, ...);
+void clear_error();
+gp_status hip_fail(hipError_t e, const char *where);
+
+hipError_t hmc_kickoff_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
+hipError_t hmc_kickoff_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
+hipError_t hmc_tiles_f32(void *, int, int, hipStream_t);
+hipError_t hmc_tiles_f64(void *, int, int, hipStream_t);
+hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, hipStream_t);
+hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, hipStream_t);
+hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
+                              int, hipStream_t);
+hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
+                              int, hipStream_t);
+hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
+hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
+hipError_t hmc_check_f32(void *, int, hipStream_t);
+hipError_t hmc_check_f64(void *, int, hipStream_t);
+
+namespace {
+
+struct InstInfo {
+  int64_t n, off, xoff;
+  int d, dp, nth;
+};
+
+struct ChainLayout {
+  size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains;
+  std::vector<size_t> per_chain;  // offset of each chain's region
+  std::vector<int> n_rb, n_cs;
+  size_t total;
+};
+
+size_t chain_bytes(int prec) { return prec == GP_F64 ? sizeof(HmcChain<double>) : sizeof(HmcChain<float>); }
+
+int plain_splits(int64_t n) {
+  const int64_t rb = (n + kHmcTile - 1) / kHmcTile;
+  int64_t s = (1024 + rb - 1) / rb;
+  const int64_t smax = std::max<int64_t>(1, n / 512);
+  s = std::min<int64_t>(std::min<int64_t>(s, smax), 64);
+  return (int)std::max<int64_t>(1, s);
 }
+
+size_t region_bytes(const InstInfo &in, int prec, int n_cs) {
+  const size_t es = prec == GP_F64 ? 8 : 4;
+  const int64_t n = in.n;
+  const int n_rb = (int)((n + kHmcTile - 1) / kHmcTile);
+  size_t o = 0;
+  o += align256(es * n * in.dp);     // xs
+  o += 4 * align256(es * n);         // r, p, q, x0
+  o += align256(es * 2 * n);         // Z
+  if (n_cs > 1) o += align256(sizeof(double) * n_cs * n);
+  o += align256(sizeof(double) * (size_t)n_rb * n_cs * kHmcRec);
+  return o;
+}
+
+ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode) {
+  ChainLayout L;
+  const int nc = (int)inst.size() * chains;
+  size_t o = 0;
+  L.hdr_word = o;
+  o = align256(o + 8 * (size_t)nc);
+  L.hdr_fin = o;
+  o = align256(o + 4 * (size_t)nc);
+  L.hdr_cnt = o;
+  o = align256(o + 16);
+  L.hdr_order = o;
+  o = align256(o + 4 * (size_t)nc);
+  L.chains = o;
+  o = align256(o + chain_bytes(prec) * (size_t)nc);
+  for (const InstInfo &in : inst) {
+    const int n_cs = mode == GP_HMC_PLAIN ? plain_splits(in.n) : 1;
+    const int n_rb = (int)((in.n + kHmcTile - 1) / kHmcTile);
+    for (int h = 0; h < chains; ++h) {
+      L.per_chain.push_back(o);
+      L.n_rb.push_back(n_rb);
+      L.n_cs.push_back(n_cs);
+      o += region_bytes(in, prec, n_cs);
+    }
+  }
+  L.total = o;
+  return L;
+}
+
+gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
+                  std::vector<InstInfo> &inst) {
+  if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
+  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD) return fail(GP_ERR_ARG, "bad kernel kind");
+  if (k->prec != GP_F64 && k->prec != GP_F32)
+    return fail(GP_ERR_UNSUPPORTED, "gp_hmc_leapfrog runs in GP_F64 or GP_F32");
+  if (k->flags != 0) return fail(GP_ERR_ARG, "kernel flags must be 0 for gp_hmc_leapfrog");
+  if (!p) return fail(GP_ERR_ARG, "params are NULL");
+  if (p->n_steps < 0) return fail(GP_ERR_ARG, "n_steps < 0");
+  if (!(p->cg_tol > 0.0)) return fail(GP_ERR_ARG, "cg_tol must be > 0");
+  if (p->cg_maxit < 1) return fail(GP_ERR_ARG, "cg_maxit must be >= 1");
+  if (p->mode != GP_HMC_PLAIN && p->mode != GP_HMC_BATCHED && p->mode != GP_HMC_GRAPH)
+    return fail(GP_ERR_ARG, "unknown mode %d", p->mode);
+  if (!b) return fail(GP_ERR_ARG, "batch is NULL");
+  if (b->n_inst < 1 || b->chains_per_inst < 1)
+    return fail(GP_ERR_SHAPE, "n_inst and chains_per_inst must be >= 1");
+  if (!b->n_points || !b->offsets) return fail(GP_ERR_ARG, "n_points and offsets are required");
+  inst.clear();
+  int64_t xo = 0;
+  for (int i = 0; i < b->n_inst; ++i) {
+    InstInfo in;
+    in.n = b->n_points[i];
+    in.off = b->offsets[i];
+    in.d = b->d ? b->d[i] : k->d;
+    if (in.n < 1) return fail(GP_ERR_SHAPE, "instance %d has n = %lld", i, (long long)in.n);
+    if (in.off < 0) return fail(GP_ERR_SHAPE, "instance %d has a negative offset", i);
+    if (in.d < 1 || in.d > kMaxD) return fail(GP_ERR_SHAPE, "instance %d has d = %d", i, in.d);
+    in.dp = padded_dim(in.d);
+    in.nth = k->kind == GP_SE_ISO ? 3 : in.d + 2;
+    in.xoff = b->x_offsets ? b->x_offsets[i] : in.off * in.d;
+    if (in.xoff < 0) return fail(GP_ERR_SHAPE, "instance %d has a negative x offset", i);
+    (void)xo;
+    inst.push_back(in);
+  }
+  // row ranges must not overlap
+  std::vector<int> idx(inst.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int c) { return inst[a].off < inst[c].off; });
+  for (size_t t = 1; t < idx.size(); ++t)
+    if (inst[idx[t - 1]].off + inst[idx[t - 1]].n > inst[idx[t]].off)
+      return fail(GP_ERR_ARG, "row ranges of instances %d and %d overlap", idx[t - 1], idx[t]);
+  return GP_OK;
+}
+
+template <typename T>
+void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const ChainLayout &L,
+                 char *ws,
+                 const void *X, const void *y, const void *phi, double *theta, double *pi,
+                 void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
+                 int32_t *status, int32_t *iters, std::vector<HmcChain<T>> &out) {
+  out.assign(inst.size() * chains, HmcChain<T>());
+  int64_t tofs = 0;
+  int c = 0;
+  for (size_t b = 0; b < inst.size(); ++b) {
+    const InstInfo &in = inst[b];
+    for (int h = 0; h < chains; ++h, ++c) {
+      HmcChain<T> &ch = out[c];
+      memset(&ch, 0, sizeof(ch));
+      ch.X = (const T *)X + in.xoff;
+      ch.y = (const T *)y + in.off;
+      const int64_t vo = (int64_t)chains * in.off + (int64_t)h * in.n;
+      ch.phi = (const T *)phi + vo;
+      ch.x = (T *)x_warm + vo;
+      const int64_t to = (int64_t)chains * tofs + (int64_t)h * in.nth;
+      ch.theta = theta + to;
+      ch.pi = pi + to;
+      ch.u = u ? u + c : nullptr;
+      ch.H0out = H0 + c;
+      ch.H1out = H1 + c;
+      ch.acc_out = acc + c;
+      ch.status_out = status + c;
+      ch.iters_out = iters ? iters + c : nullptr;
+      ch.n = in.n;
+      ch.d = in.d;
+      ch.dp = in.dp;
+      ch.kind = kind;
+      ch.nth = in.nth;
+      char *r = ws + L.per_chain[c];
+      const size_t es = sizeof(T);
+      const int64_t n = in.n;
+      ch.xs = (T *)r;
+      r += align256(es * n * in.dp);
+      const size_t vb = align256(es * n);
+      ch.r = (T *)r;
+      ch.p = (T *)(r + vb);
+      ch.q = (T *)(r + 2 * vb);
+      ch.x0 = (T *)(r + 3 * vb);
+      r += 4 * vb;
+      ch.Z = (T *)r;
+      r += align256(es * 2 * n);
+      ch.n_rb = L.n_rb[c];
+      ch.n_cs = L.n_cs[c];
+      ch.n_jobs = ch.n_rb * ch.n_cs;
+      ch.col_chunk = (n + ch.n_cs - 1) / ch.n_cs;
+      if (ch.n_cs > 1) {
+        ch.qpart = (double *)r;
+        r += align256(sizeof(double) * ch.n_cs * n);
+      }
+      ch.rec = (double *)r;
+    }
+    tofs += in.nth;
+  }
+}
+
+struct GraphEntry {
+  std::vector<char> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+std::mutex g_mu;
+std::map<void *, std::vector<char>> g_uploaded;  // ws -> descriptor bytes last uploaded
+std::map<void *, GraphEntry> g_graphs;           // ws -> captured trajectory
+
+}  // namespace
+}  // namespace gpk
+
+using namespace gpk;
 
 extern "C" {
 
 size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b) {
-  (void)k; (void)p; (void)b;
-  return 0;
+  std::vector<InstInfo> inst;
+  if (collect(k, p, b, inst) != GP_OK) return 0;
+  return make_layout(inst, b->chains_per_inst, k->prec, p->mode).total;
 }
 
 gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
@@ -18,10 +228,170 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
                           double *pi, void *x_warm, const double *u_accept, double *H0,
                           double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
                           void *ws, size_t ws_bytes, hipStream_t stream) {
-  (void)k; (void)p; (void)b; (void)X; (void)y; (void)phi; (void)theta; (void)pi; (void)x_warm;
-  (void)u_accept; (void)H0; (void)H1; (void)accepted; (void)status; (void)cg_iters; (void)ws;
-  (void)ws_bytes; (void)stream;
-  return gpk::fail(GP_ERR_UNSUPPORTED, "gp_hmc_leapfrog is not available in this build");
+  clear_error();
+  std::vector<InstInfo> inst;
+  gp_status st = collect(k, p, b, inst);
+  if (st) return st;
+  if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status)
+    return fail(GP_ERR_ARG, "X, y, phi, theta, pi, x_warm, H0, H1, accepted and status must be non-NULL");
+  const int chains = b->chains_per_inst;
+  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode);
+  if (!ws || ws_bytes < L.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                ws ? ws_bytes : (size_t)0);
+  const int nc = (int)inst.size() * chains;
+  char *w = (char *)ws;
+
+  std::vector<char> desc;
+  if (k->prec == GP_F64) {
+    std::vector<HmcChain<double>> v;
+    fill_chains<double>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+                        accepted, status, cg_iters, v);
+    desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
+  } else {
+    std::vector<HmcChain<float>> v;
+    fill_chains<float>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+                       accepted, status, cg_iters, v);
+    desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
+  }
+  // chain order for the batched scheduler: largest problems first
+  std::vector<unsigned> order(nc);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](unsigned a, unsigned c) {
+    return inst[a / chains].n * inst[a / chains].n * inst[a / chains].dp >
+           inst[c / chains].n * inst[c / chains].n * inst[c / chains].dp;
+  });
+  std::vector<char> upload = desc;
+  upload.insert(upload.end(), (const char *)order.data(), (const char *)(order.data() + nc));
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  hipError_t e;
+  auto itu = g_uploaded.find(ws);
+  const bool changed = itu == g_uploaded.end() || itu->second != upload;
+  if (changed) {
+    // the workspace may still be in use by earlier work on the stream
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "stream sync");
+    e = hipMemcpy(w + L.chains, desc.data(), desc.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hipMemcpy(w + L.hdr_order, order.data(), sizeof(unsigned) * nc, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "order upload");
+    g_uploaded[ws] = upload;
+    auto itg = g_graphs.find(ws);
+    if (itg != g_graphs.end()) {
+      hipGraphExecDestroy(itg->second.exec);
+      g_graphs.erase(itg);
+    }
+  }
+
+  HmcRunParams prm;
+  prm.n_steps = p->n_steps;
+  prm.dt = p->dt;
+  prm.tol2 = p->cg_tol * p->cg_tol;
+  prm.cg_maxit = p->cg_maxit;
+  prm.max_jobs = (int)std::min<int64_t>((int64_t)(p->n_steps + 2) * (p->cg_maxit + 2) + 4,
+                                        (int64_t)1 << 30);
+  HmcQueue qu;
+  qu.word = (unsigned long long *)(w + L.hdr_word);
+  qu.finished = (unsigned *)(w + L.hdr_fin);
+  qu.chains_done = (unsigned *)(w + L.hdr_cnt);
+  qu.abort = (unsigned *)(w + L.hdr_cnt + 4);
+  qu.order = (unsigned *)(w + L.hdr_order);
+  void *chains_dev = w + L.chains;
+  const bool f64 = k->prec == GP_F64;
+  const size_t cb = chain_bytes(k->prec);
+
+  if (p->mode == GP_HMC_PLAIN) {
+    for (int c = 0; c < nc; ++c) {
+      void *cp = (char *)chains_dev + cb * c;
+      e = f64 ? hmc_kickoff_f64(cp, 1, prm, qu, 0, stream) : hmc_kickoff_f32(cp, 1, prm, qu, 0, stream);
+      if (e != hipSuccess) return hip_fail(e, "kickoff");
+      const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
+      const size_t off_done = f64 ? offsetof(HmcChain<double>, done) : offsetof(HmcChain<float>, done);
+      const int n_jobs = L.n_rb[c] * L.n_cs[c];
+      for (int64_t guard = 0;; ++guard) {
+        if (guard > (int64_t)prm.max_jobs + 2)
+          return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
+        int done = 0;
+        e = hipMemcpyAsync(&done, (char *)cp + off_done, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
+        if (done) break;
+        const int dpc = inst[c / chains].dp;
+        e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);
+        if (e == hipSuccess)
+          e = f64 ? hmc_epilogue_f64(cp, prm, stream) : hmc_epilogue_f32(cp, prm, stream);
+        if (e != hipSuccess) return hip_fail(e, "plain-mode step");
+      }
+      (void)off_job;
+    }
+    return GP_OK;
+  }
+
+  int dev = 0, cus = 256, clk_khz = 100000;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
+  int64_t total_jobs = 0;
+  for (int c = 0; c < nc; ++c) total_jobs += (int64_t)L.n_rb[c] * L.n_cs[c];
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 4, total_jobs));
+  int dpmax = 4;
+  for (const InstInfo &in : inst) dpmax = std::max(dpmax, in.dp);
+  // an idle workgroup gives up after 20 s without claimable work
+  const long long idle_limit = (long long)clk_khz * 1000LL * 20LL;
+
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t r = f64 ? hmc_reset_f64(qu, s) : hmc_reset_f32(qu, s);
+    if (r != hipSuccess) return r;
+    r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
+            : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
+    if (r != hipSuccess) return r;
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, s)
+            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, s);
+    if (r != hipSuccess) return r;
+    return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
+  };
+
+  if (p->mode == GP_HMC_BATCHED) {
+    e = enqueue(stream);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return GP_OK;
+  }
+
+  // GP_HMC_GRAPH: capture once per (workspace, descriptors, parameters), then replay.
+  std::vector<char> key((const char *)&prm, (const char *)(&prm + 1));
+  key.insert(key.end(), (const char *)&grid, (const char *)(&grid + 1));
+  key.insert(key.end(), (const char *)&dpmax, (const char *)(&dpmax + 1));
+  GraphEntry &ge = g_graphs[ws];
+  if (!ge.exec || ge.key != key) {
+    if (ge.exec) {
+      hipGraphExecDestroy(ge.exec);
+      ge.exec = nullptr;
+    }
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t graph;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t el = enqueue(cap);
+      e = hipStreamEndCapture(cap, &graph);
+      if (el != hipSuccess) e = el;
+    }
+    if (e == hipSuccess) {
+      e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+    }
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      ge.exec = nullptr;
+      return hip_fail(e, "graph capture");
+    }
+    ge.key = key;
+  }
+  e = hipGraphLaunch(ge.exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return GP_OK;
 }
 
-}
+}  // extern "C"

@@ -170,7 +170,10 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
 #pragma unroll
   for (int ib = 0; ib < IB; ++ib) {
     int64_t i = row0 + ib * 16 + m;
-    if (i >= a.n) i = a.n - 1;
+    // rows past the end reuse the last row's coordinates but get a zero P operand, so their
+    // quad weights, and with them every gradient contribution, vanish
+    const bool row_ok = i < a.n;
+    if (!row_ok) i = a.n - 1;
 #pragma unroll
     for (int k = 0; k < D; ++k) xi[ib][k] = a.xs[i * XS + k];
     if (GM) {
@@ -179,7 +182,9 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int c = 8 * g + q;
-        v[q] = c < R ? (float)((double)a.P[i * a.ldp + c] * (a.w ? a.w[c] : 1.0)) * sP : 0.0f;
+        v[q] = (row_ok && c < R)
+                   ? (float)((double)a.P[i * a.ldp + c] * (a.w ? a.w[c] : 1.0)) * sP
+                   : 0.0f;
       }
 #pragma unroll
       for (int q = 0; q < 8; q += 2) {

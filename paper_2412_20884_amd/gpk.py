@@ -18,7 +18,7 @@ ISO, ARD = 0, 1
 F64, F32, BF16X = 0, 1, 2
 NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
-CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA = 1, 2, 4
+CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED = 1, 2, 4, 8
 
 EXPORTED = (
     "gp_last_error", "gp_status_string", "gp_n_theta", "gp_workspace_size", "gp_kmatvec",
@@ -206,3 +206,57 @@ def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=
                                   r, _p(AV), r, _p(wk), 0 if wk is None else wk.numel(),
                                   _stream(dev)))
     return {"grad": grad, "quad": quad, "AU": AU, "AV": AV}
+
+
+_HMC_WS = {}
+
+
+def hmc_workspace_size(kernel, params, batch):
+    return int(lib().gp_hmc_workspace_size(ctypes.byref(kernel), ctypes.byref(params), ctypes.byref(batch)))
+
+
+def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, d=None,
+                 x_offsets=None, u=None, n_steps=20, dt=1e-2, cg_tol=1e-6, cg_maxit=1000,
+                 mode=BATCHED, ws=None, cg_iters=True):
+    """One HMC trajectory per chain through gp_hmc_leapfrog (packing as in include/gpk.h).
+
+    theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, cg_iters).
+    The workspace is kept per (device, size) so repeated calls reuse it (and a captured graph).
+    """
+    dev = X.device
+    dt_ = X.dtype
+    _same(dev, dt_, y=y, phi=phi, x_warm=x_warm)
+    _same(dev, torch.float64, theta=theta, pi=pi, u=u)
+    for name, t in (("X", X), ("y", y), ("phi", phi), ("theta", theta), ("pi", pi), ("x_warm", x_warm)):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    n_inst = len(n_points)
+    dims = [X.shape[1]] * n_inst if d is None else list(d)
+    k = Kernel(kind_code(kind), prec_code(dt_), int(max(dims)), 0)
+    prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode))
+    npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
+    offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
+    dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
+    xo = (ctypes.c_int64 * n_inst)(*[int(v) for v in x_offsets]) if x_offsets is not None else None
+    b = Batch(n_inst, int(chains), npts, offs, dd, xo)
+    nc = n_inst * chains
+    H0 = torch.empty(nc, dtype=torch.float64, device=dev)
+    H1 = torch.empty(nc, dtype=torch.float64, device=dev)
+    acc = torch.empty(nc, dtype=torch.int32, device=dev)
+    st = torch.empty(nc, dtype=torch.int32, device=dev)
+    it = torch.empty(nc, dtype=torch.int32, device=dev) if cg_iters else None
+    nbytes = hmc_workspace_size(k, prm, b)
+    if nbytes == 0:
+        _check(lib().gp_hmc_leapfrog(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, None,
+                                     None, None, None, None, None, None, None, None, None, None,
+                                     None, 0, None))
+    if ws is None:
+        key = (str(dev), nbytes)
+        ws = _HMC_WS.get(key)
+        if ws is None:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            _HMC_WS[key] = ws
+    _check(lib().gp_hmc_leapfrog(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), _p(X), _p(y),
+                                 _p(phi), _p(theta), _p(pi), _p(x_warm), _p(u), _p(H0), _p(H1),
+                                 _p(acc), _p(st), _p(it), _p(ws), ws.numel(), _stream(dev)))
+    return {"H0": H0, "H1": H1, "accepted": acc, "status": st, "cg_iters": it}

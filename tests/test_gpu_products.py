@@ -98,7 +98,8 @@ def test_quadform_symmetric(dtype, kind, d, n):
     scale = _grad_scale(X, th, kind, U, U, w)
     tol = TOL[dtype]
     assert grad_rel_err(host(res["grad"]), ref["grad"], scale) < tol
-    assert col_rel_err(host(res["quad"])[None, :], ref["quad"][None, :]) < tol * 10
+    qscale = np.diag(np.abs(U).T @ ogp.matvec(X, th, kind, np.abs(U)))
+    assert np.max(np.abs(host(res["quad"]) - ref["quad"]) / qscale) < tol
     assert col_rel_err(host(res["AU"]), ref["AU"]) < tol
     assert col_rel_err(host(res["AV"]), ref["AV"]) < tol
 
@@ -151,3 +152,66 @@ def test_determinism_bitwise():
     torch.cuda.synchronize()
     assert torch.equal(a["grad"], b["grad"]) and torch.equal(a["AU"], b["AU"])
     assert torch.equal(a["quad"], b["quad"])
+
+
+# ---- matrix-core (fp16 hi/lo split) path: float inputs, 8 <= R <= 32, d <= 16 ---------------
+
+@pytest.mark.parametrize("kind,d", [("iso", 1), ("iso", 3), ("iso", 4), ("ard", 2), ("ard", 8),
+                                    ("ard", 13), ("ard", 16)])
+@pytest.mark.parametrize("r", [8, 16, 20, 32])
+@pytest.mark.parametrize("n", [300, 5003])
+def test_quadform_mfma_symmetric(kind, d, r, n):
+    p = _problem(kind, n, d, 500 + 7 * d + r + n, r)
+    X, U = rounded(p["X"], torch.float32), rounded(p["U"], torch.float32)
+    w = np.linspace(-1.0, 2.0, r)
+    th = p["theta"]
+    Ud = to_dev(U, torch.float32)
+    res = gpk.quadform_grad(to_dev(X, torch.float32), to_dev(th, torch.float64), Ud, Ud,
+                            to_dev(w, torch.float64), kind, want_AU=True)
+    torch.cuda.synchronize()
+    ref = ogp.quadform_grad(X, th, kind, U, U, w)
+    assert col_rel_err(host(res["AU"]), ref["AU"]) < 1e-5
+    assert grad_rel_err(host(res["grad"]), ref["grad"], _grad_scale(X, th, kind, U, U, w)) < 1e-5
+    qscale = np.diag(np.abs(U).T @ ogp.matvec(X, th, kind, np.abs(U)))
+    assert np.max(np.abs(host(res["quad"]) - ref["quad"]) / qscale) < 1e-5
+
+
+@pytest.mark.parametrize("want", ["AU", "AV", "both"])
+@pytest.mark.parametrize("n", [1000, 6000])
+def test_quadform_mfma_unsymmetric(want, n):
+    p = _problem("ard", n, 6, 91 + n, 16)
+    X, U, V = (rounded(p[k], torch.float32) for k in ("X", "U", "V"))
+    th = p["theta"]
+    w = np.linspace(0.5, 1.5, 16)
+    res = gpk.quadform_grad(to_dev(X, torch.float32), to_dev(th, torch.float64),
+                            to_dev(U, torch.float32), to_dev(V, torch.float32),
+                            to_dev(w, torch.float64), "ard", want_AU=want in ("AU", "both"),
+                            want_AV=want in ("AV", "both"))
+    torch.cuda.synchronize()
+    ref = ogp.quadform_grad(X, th, "ard", U, V, w)
+    assert grad_rel_err(host(res["grad"]), ref["grad"], _grad_scale(X, th, "ard", U, V, w)) < 1e-5
+    qscale = np.abs(U).T @ ogp.matvec(X, th, "ard", np.abs(V))
+    assert np.max(np.abs(host(res["quad"]) - ref["quad"]) / np.diag(qscale)) < 1e-5
+    if want in ("AU", "both"):
+        assert col_rel_err(host(res["AU"]), ref["AU"]) < 1e-5
+    if want in ("AV", "both"):
+        assert col_rel_err(host(res["AV"]), ref["AV"]) < 1e-5
+
+
+@pytest.mark.parametrize("mag", [1e-6, 1e5])
+@pytest.mark.parametrize("log_alpha", [-4.0, 6.0])
+def test_mfma_operand_scaling(mag, log_alpha):
+    # operands far from unit scale and alpha far from 1 exercise the power-of-two scaling
+    p = I.iso_problem(2100, 2, 17, ell=0.2, sigma2=1e-2, r=16)
+    th = p["theta"].copy()
+    th[0] = log_alpha
+    X = rounded(p["X"], torch.float32)
+    V = rounded(p["V"] * mag, torch.float32)
+    out = gpk.kmatvec(to_dev(X, torch.float32), to_dev(th, torch.float64), to_dev(V, torch.float32), "iso")
+    res = gpk.quadform_grad(to_dev(X, torch.float32), to_dev(th, torch.float64),
+                            to_dev(V, torch.float32), None, None, "iso")
+    torch.cuda.synchronize()
+    ref = ogp.quadform_grad(X, th, "iso", V, V)
+    assert col_rel_err(host(out), ref["AV"]) < 1e-5
+    scale = _grad_scale(X, th, "iso", V, V, np.ones(16))
+    assert grad_rel_err(host(res["grad"]), ref["grad"], scale) < 1e-5
