@@ -115,8 +115,11 @@ def cpu_baseline(budget_s=15.0):
                       f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad"}
 
 
-def bench_leapfrog(modes=("graph", "plain")):
-    """Chain-leapfrog-steps/s on the batched workload, batched (graph replay) vs plain."""
+def bench_leapfrog(modes=("graph", "plain"), subset=8):
+    """Chain-leapfrog-steps/s on the batched workload, batched (graph replay) vs plain.
+
+    subset = k times every k-th instance (k = 1: all 64 instances).
+    """
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
@@ -124,7 +127,7 @@ def bench_leapfrog(modes=("graph", "plain")):
     dev = "cuda:0"
     wl = inputs.batched()
     C = wl["chains"]
-    inst = wl["instances"]
+    inst = wl["instances"][::subset]
     ns = [len(b["y"]) for b in inst]
     ds = [b["X"].shape[1] for b in inst]
     offs = np.cumsum([0] + ns[:-1])
@@ -132,7 +135,8 @@ def bench_leapfrog(modes=("graph", "plain")):
     X = torch.tensor(np.concatenate([b["X"].ravel() for b in inst]), dtype=torch.float32, device=dev)[:, None]
     y = torch.tensor(np.concatenate([b["y"] for b in inst]), dtype=torch.float32, device=dev)
     # phi = xi / sqrt(alpha + sigma^2): the cost does not depend on phi's law
-    phi = torch.tensor(np.concatenate([(b["xi"] / np.sqrt(1.0 + 1e-2)).ravel() for b in inst]),
+    s2 = float(np.exp(inst[0]["theta"][-1]))
+    phi = torch.tensor(np.concatenate([(b["xi"] / np.sqrt(1.0 + s2)).ravel() for b in inst]),
                        dtype=torch.float32, device=dev)
     th0 = np.concatenate([np.tile(b["theta"], C) for b in inst])
     pi0 = np.concatenate([b["pi"].ravel() for b in inst])
@@ -145,27 +149,72 @@ def bench_leapfrog(modes=("graph", "plain")):
         pi = torch.tensor(pi0, dtype=torch.float64, device=dev)
         x = torch.zeros(sum(ns) * C, dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u,
-                               n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=1e-6, cg_maxit=2000, mode=m)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        st = res["status"].cpu().numpy()
-        its = res["cg_iters"].cpu().numpy()
+        kw = dict(n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=1e-6, cg_maxit=2000, mode=m)
+        if mode == "plain":
+            # one instance per call so progress is visible; the library runs chains one at a time
+            t = 0.0
+            sts, itl, accs = [], [], []
+            toff = 0
+            for bi in range(len(ns)):
+                nth = ds[bi] + 2
+                thb = th[toff:toff + C * nth]
+                pib = pi[toff:toff + C * nth]
+                xb = x[C * offs[bi]:C * (offs[bi] + ns[bi])]
+                Xb = X[xoffs[bi]:xoffs[bi] + ns[bi] * ds[bi]]
+                t0 = time.perf_counter()
+                r = gpk.hmc_leapfrog(Xb, y[offs[bi]:offs[bi] + ns[bi]], phi[C * offs[bi]:C * (offs[bi] + ns[bi])],
+                                     thb, pib, xb, "ard", [ns[bi]], [0], C, d=[ds[bi]],
+                                     u=u[bi * C:(bi + 1) * C], **kw)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+                sts.append(r["status"].cpu().numpy())
+                itl.append(r["cg_iters"].cpu().numpy())
+                accs.append(r["accepted"].cpu().numpy())
+                toff += C * nth
+                log(f"  plain instance {bi}: N={ns[bi]} d={ds[bi]} cumulative {t:.1f} s")
+            st = np.concatenate(sts)
+            its = np.concatenate(itl)
+            acc = np.concatenate(accs)
+        else:
+            t0 = time.perf_counter()
+            res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            st = res["status"].cpu().numpy()
+            its = res["cg_iters"].cpu().numpy()
+            acc = res["accepted"].cpu().numpy()
         thn = th.cpu().numpy()
+        h1 = res["H1"].cpu().numpy() if mode != "plain" else None
         out[mode] = {"chain_steps_per_s": len(st) * wl["n_steps"] / t, "seconds": t,
                      "mean_cg_iters_per_solve": float(its.mean() / (wl["n_steps"] + 2)),
-                     "accept_rate": float(res["accepted"].float().mean().item()),
+                     "accept_rate": float(np.mean(acc)),
                      "flagged_chains": int((st != 0).sum())}
         if ref_theta is None:
             ref_theta = thn
         else:
             out[mode]["max_abs_theta_diff_vs_" + modes[0]] = float(np.max(np.abs(thn - ref_theta)))
         log(f"leapfrog {mode}: {out[mode]}")
+        torch.cuda.empty_cache()
     if "graph" in out and "plain" in out:
         out["speedup_batched_vs_plain"] = out["graph"]["chain_steps_per_s"] / out["plain"]["chain_steps_per_s"]
-    out["workload"] = "batched: 64 instances, N_b in [2048, 32768], d_b in {4,8,16}, ARD SE, 8 chains each, 20 leapfrog steps, dt 1e-2, CG tol 1e-6, FP32"
+    out["workload"] = (f"batched: instances 0,{subset},{2 * subset},.. ({len(inst)} of 64; N_b in [2048, 32768], "
+                       f"d_b in {{4,8,16}}), ARD SE, sigma^2=0.1, 8 chains each, 20 leapfrog steps, "
+                       f"dt 1e-2, CG tol 1e-6, FP32; N_b = {ns}, d_b = {ds}")
     return out
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of a known size, run under the same profiler command so its
+    FETCH_SIZE / WRITE_SIZE readings calibrate the counters (bytes per counter unit)."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_each_way": nbytes, "copies": 3}
 
 
 def main():
@@ -177,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--leapfrog-modes", default="graph,plain")
+    ap.add_argument("--leapfrog-subset", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
@@ -188,6 +239,8 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+    if args.copy_calibration:
+        log(f"copy calibration: {copy_calibration()}")
     log("large3: generating inputs and warming up")
     b = bench_large3(args.steps, args.warmup)
     n = b["n"]
@@ -217,7 +270,7 @@ def main():
         log("cpu baseline: timing the FP64 oracle on a row slab")
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     if not args.no_leapfrog:
-        line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")))
+        line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset)
     print(json.dumps(line), flush=True)
 
 

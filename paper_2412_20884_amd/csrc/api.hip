@@ -53,7 +53,7 @@ hipError_t zero_doubles(double *a, int64_t m, hipStream_t s) {
 }
 
 int64_t pair_blocks(const PassDesc &p) {
-  const int rows = p.use_mfma ? kRowsMfma : kRowsValu;
+  const int rows = p.use_mfma ? mfma_rows_per_block(p.kind, p.d, p.P ? 1 : 0) : kRowsValu;
   return ((p.n + rows - 1) / rows) * p.splits;
 }
 
@@ -126,7 +126,8 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r) {
   const int rows = pl.use_mfma ? kRowsMfma : kRowsValu;
   pl.splits = choose_splits(n, rows);
   pl.nrec = nth_of(k) + pl.rpass;
-  const int64_t pb = ((n + rows - 1) / rows) * pl.splits;
+  const int rows_min = pl.use_mfma ? kRowsMfmaMin : kRowsValu;
+  const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.splits;
   const int64_t fb = pl.splits > 1 ? (n + kThreads - 1) / kThreads : 0;
   pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.splits, pb, fb, pl.nrec,
                    pl.use_mfma ? mfma_scratch_bytes() : 0);

@@ -32,9 +32,6 @@ namespace mf {
 
 constexpr int kWaves = 8;
 constexpr int kWG = kWaves * 64;  // 512 threads
-constexpr int IB = 2;             // 16-row blocks per wave
-constexpr int kRowsWG = kWaves * IB * 16;
-static_assert(kRowsWG == kRowsMfma, "rows per block");
 constexpr int TJ = 32;            // columns per tile
 constexpr int kStrideH = 40;      // halves per LDS row of the split tiles (80 bytes)
 constexpr int kFold = 8;          // tiles between folds of the float partials
@@ -143,6 +140,10 @@ __global__ void scales_final(MArgs a, int *scl) {
 // D: coordinates used (1..4 stored with stride 4, or 8, 16).  RP: padded R (16 or 32).
 template <int D, int RP, int GM>
 __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
+  // 16-row blocks per wave: two, except for the per-coordinate gradient at d >= 8, whose
+  // accumulators need the registers of the second block
+  constexpr int IB = (GM == 2 && D >= 8) ? 1 : 2;
+  constexpr int kRowsWG = kWaves * IB * 16;
   constexpr int XS = D <= 4 ? 4 : D;         // LDS/global stride of a point
   constexpr int NCB = RP / 16;               // 16-column blocks of the product
   constexpr int NG = GM == 2 ? D : 1;
@@ -199,8 +200,11 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
 
   f32x4 acc[IB][NCB];
   double acc64[IB][NCB][4];
-  float gl[IB][NG];
-  double gl64[NG];
+  // gradient partials: float per lane over kFold tiles, then (iso) a double per lane or
+  // (ARD) a wave reduction into per-wave double slots in LDS
+  float gl[NG];
+  double gl64 = 0.0;
+  __shared__ double glsh[kWaves][GM == 2 ? D : 1];
 #pragma unroll
   for (int ib = 0; ib < IB; ++ib)
 #pragma unroll
@@ -210,11 +214,8 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
       for (int r = 0; r < 4; ++r) acc64[ib][cb][r] = 0.0;
     }
 #pragma unroll
-  for (int k = 0; k < NG; ++k) {
-    gl64[k] = 0.0;
-#pragma unroll
-    for (int ib = 0; ib < IB; ++ib) gl[ib][k] = 0.0f;
-  }
+  for (int k = 0; k < NG; ++k) gl[k] = 0.0f;
+  if (GM == 2 && lane < NG) glsh[wave][lane] = 0.0;
   const double unscale_out = ldexp(1.0, -(eK + eY));
   const double unscale_g = ldexp(1.0, -(eK + eP + eQ));
 
@@ -223,55 +224,72 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   const int ntiles = (int)((j1 - j0 + TJ - 1) / TJ);
   const bool sym = (a.Y == a.Q && a.ldy == a.ldq);
 
-  // Stage tile t (columns j0 + 32 t ..) into LDS buffer b.  Out-of-range columns are zero in
-  // Y and Q, and their coordinates are pushed far away so their kernel values vanish.
-  auto stage = [&](int t, int b) {
+  // Column tiles are software-pipelined: the global loads of tile t + 2 are issued before the
+  // compute of tile t + 1 and land in registers; after the compute of tile t the registers of
+  // tile t + 1 are split and written to the other LDS buffer.  Out-of-range columns are zero
+  // in Y and Q and their coordinates are pushed far away so their kernel values vanish.
+  constexpr int NE = (TJ * RP + kWG - 1) / kWG;  // Y/Q elements per thread per tile
+  constexpr int NX = TJ * XS;                     // coordinate elements per tile
+  float ry[NE], rq[NE], rx = 0.0f;
+  auto prefetch = [&](int t) {
     const int64_t jt = j0 + (int64_t)t * TJ;
-    for (int e = tid; e < TJ * XS; e += kWG) {
-      const int jj = e / XS, k = e - jj * XS;
-      const int64_t j = jt + jj;
-      sx[b][e] = j < j1 ? a.xs[j * XS + k] : (k == 0 ? 1.0e18f : 0.0f);
-    }
-    for (int e = tid; e < TJ * RP; e += kWG) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * kWG;
       const int jj = e / RP, c = e - jj * RP;
       const int64_t j = jt + jj;
-      const bool ok = j < j1 && c < R;
-      const float yv = ok ? a.Y[j * a.ldy + c] * sY : 0.0f;
-      float h, l;
-      split(yv, h, l);
-      // slot of column jj in the transposed product operand
-      const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
-      const int slot = 8 * gg + q;
-      syh[b][c * kStrideH + slot] = (_Float16)h;
-      syl[b][c * kStrideH + slot] = (_Float16)l;
-      if (GM) {
-        float qh, ql;
-        if (sym) {
-          const float qv = ok ? a.Y[j * a.ldy + c] * sQ : 0.0f;
-          split(qv, qh, ql);
-        } else {
-          const float qv = ok ? a.Q[j * a.ldq + c] * sQ : 0.0f;
-          split(qv, qh, ql);
-        }
-        sqh[b][jj * kStrideH + c] = (_Float16)qh;
-        sql[b][jj * kStrideH + c] = (_Float16)ql;
-      }
+      const bool ok = e < TJ * RP && j < j1 && c < R;
+      ry[u] = ok ? a.Y[j * a.ldy + c] : 0.0f;
+      if (GM && !sym) rq[u] = ok ? a.Q[j * a.ldq + c] : 0.0f;
     }
-    if (GM && RP < 32) {
-      // zero the unused half of the S contraction (c = RP .. 31)
-      for (int e = tid; e < TJ * (32 - RP); e += kWG) {
-        const int jj = e / (32 - RP), c = RP + (e - jj * (32 - RP));
-        sqh[b][jj * kStrideH + c] = (_Float16)0.0f;
-        sql[b][jj * kStrideH + c] = (_Float16)0.0f;
-      }
+    if (tid < NX) {
+      const int jj = tid / XS, k = tid - jj * XS;
+      const int64_t j = jt + jj;
+      rx = j < j1 ? a.xs[j * XS + k] : (k == 0 ? 1.0e18f : 0.0f);
     }
   };
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * kWG;
+      if (e < TJ * RP) {
+        const int jj = e / RP, c = e - jj * RP;
+        float h, l;
+        split(ry[u] * sY, h, l);
+        // slot of column jj in the transposed product operand
+        const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
+        const int slot = 8 * gg + q;
+        syh[b][c * kStrideH + slot] = (_Float16)h;
+        syl[b][c * kStrideH + slot] = (_Float16)l;
+        if (GM) {
+          float qh, ql;
+          split((sym ? ry[u] : rq[u]) * sQ, qh, ql);
+          sqh[b][jj * kStrideH + c] = (_Float16)qh;
+          sql[b][jj * kStrideH + c] = (_Float16)ql;
+        }
+      }
+    }
+    if (tid < NX) sx[b][tid] = rx;
+  };
+  if (GM && RP < 32) {
+    // the unused half of the S contraction (c = RP .. 31) stays zero in both buffers
+    for (int e = tid; e < 2 * TJ * (32 - RP); e += kWG) {
+      const int bb = e / (TJ * (32 - RP));
+      const int r2 = e - bb * TJ * (32 - RP);
+      const int jj = r2 / (32 - RP), c = RP + (r2 - jj * (32 - RP));
+      sqh[bb][jj * kStrideH + c] = (_Float16)0.0f;
+      sql[bb][jj * kStrideH + c] = (_Float16)0.0f;
+    }
+  }
 
-  if (ntiles > 0) stage(0, 0);
+  if (ntiles > 0) {
+    prefetch(0);
+    commit(0);
+  }
+  if (ntiles > 1) prefetch(1);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     const int b = t & 1;
-    if (t + 1 < ntiles) stage(t + 1, b ^ 1);
     // ---- S^T for both 16-column halves and all row blocks -------------------------------
     f32x4 s[IB][2];
     if (GM) {
@@ -296,52 +314,47 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
     H8 kh[IB], kl[IB];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) {
+      float kv[IB][4];
 #pragma unroll
-      for (int r = 0; r < 4; r += 2) {
-        float xj0[D], xj1[D];
+      for (int r = 0; r < 4; ++r) {
+        float xj[D];
         const float *p0 = &sx[b][(16 * jb + 4 * g + r) * XS];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          xj0[k] = p0[k];
-          xj1[k] = p0[XS + k];
-        }
+        for (int k = 0; k < D; ++k) xj[k] = p0[k];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
-          float d20[D], d21[D];
-          float rho0 = 0.f, rho1 = 0.f;
+          float d2[GM == 2 ? D : 1];
+          float rho = 0.f;
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            const float u0 = xi[ib][k] - xj0[k];
-            const float u1 = xi[ib][k] - xj1[k];
+            const float u = xi[ib][k] - xj[k];
             if (GM == 2) {
-              d20[k] = u0 * u0;
-              d21[k] = u1 * u1;
-              rho0 += d20[k];
-              rho1 += d21[k];
+              d2[k] = u * u;
+              rho += d2[k];
             } else {
-              rho0 = fmaf(u0, u0, rho0);
-              rho1 = fmaf(u1, u1, rho1);
+              rho = fmaf(u, u, rho);
             }
           }
-          const float k0 = __builtin_amdgcn_exp2f(c0 - rho0);
-          const float k1 = __builtin_amdgcn_exp2f(c0 - rho1);
+          const float kk = __builtin_amdgcn_exp2f(c0 - rho);
           if (GM) {
-            const float W0 = k0 * s[ib][jb][r];
-            const float W1 = k1 * s[ib][jb][r + 1];
+            const float W = kk * s[ib][jb][r];
             if (GM == 1) {
-              gl[ib][0] = fmaf(W0, rho0, gl[ib][0]);
-              gl[ib][0] = fmaf(W1, rho1, gl[ib][0]);
+              gl[0] = fmaf(W, rho, gl[0]);
             } else {
 #pragma unroll
-              for (int k = 0; k < D; ++k) {
-                gl[ib][k] = fmaf(W0, d20[k], gl[ib][k]);
-                gl[ib][k] = fmaf(W1, d21[k], gl[ib][k]);
-              }
+              for (int k = 0; k < D; ++k) gl[k] = fmaf(W, d2[k], gl[k]);
             }
           }
+          kv[ib][r] = kk;
+        }
+      }
+#pragma unroll
+      for (int ib = 0; ib < IB; ++ib) {
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
           float h0, l0, h1, l1;
-          split(k0, h0, l0);
-          split(k1, h1, l1);
+          split(kv[ib][r], h0, l0);
+          split(kv[ib][r + 1], h1, l1);
           kh[ib].u[2 * jb + r / 2] = pk_rtz(h0, h1);
           kl[ib].u[2 * jb + r / 2] = pk_rtz(l0, l1);
         }
@@ -362,6 +375,8 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
         acc[ib][cb] = z;
       }
     }
+    if (t + 1 < ntiles) commit(b ^ 1);
+    if (t + 2 < ntiles) prefetch(t + 2);
     if ((t + 1) % kFold == 0 || t + 1 == ntiles) {
 #pragma unroll
       for (int ib = 0; ib < IB; ++ib)
@@ -371,14 +386,15 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
           for (int r = 0; r < 4; ++r) acc64[ib][cb][r] += (double)acc[ib][cb][r];
           acc[ib][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-      if (GM) {
+      if (GM == 1) {
+        gl64 += (double)gl[0];
+        gl[0] = 0.0f;
+      } else if (GM == 2) {
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
-#pragma unroll
-          for (int ib = 0; ib < IB; ++ib) {
-            gl64[k] += (double)gl[ib][k];
-            gl[ib][k] = 0.0f;
-          }
+          const double v = wave_sum((double)gl[k]);
+          if (lane == 0) glsh[wave][k] += v;
+          gl[k] = 0.0f;
         }
       }
     }
@@ -440,14 +456,15 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
     if (tid == 0) rec[0] = t;
   }
   for (int k = 0; k < a.L; ++k) {
-    double v = 0.0;
-    if (GM == 1) v = gl64[0];
+    double t;
     if (GM == 2) {
-#pragma unroll
-      for (int kk = 0; kk < NG; ++kk)
-        if (kk == k) v = gl64[kk];
+      __syncthreads();
+      t = 0.0;
+      for (int w_ = 0; w_ < kWaves; ++w_) t += glsh[w_][k];
+      t *= unscale_g;
+    } else {
+      t = block_total(GM == 1 ? gl64 * unscale_g : 0.0);
     }
-    const double t = block_total(v * unscale_g);
     if (tid == 0) rec[1 + k] = t;
   }
   {
@@ -530,6 +547,15 @@ static void launch_d_rp(const MArgs &ma, int gm, dim3 grid, hipStream_t s) {
     pair_mfma<D, RP, 2><<<grid, kWG, 0, s>>>(ma);
 }
 
+}  // namespace mf
+
+int mfma_rows_per_block(int kind, int d, int has_grad) {
+  const int dd = d <= 4 ? d : (d <= 8 ? 8 : 16);
+  return (has_grad && kind != 0 && dd >= 8) ? mf::kWaves * 16 : mf::kWaves * 32;
+}
+
+namespace mf {
+
 template <int D>
 static void launch_d(const MArgs &ma, int rp, int gm, dim3 grid, hipStream_t s) {
   if (rp == 16)
@@ -583,7 +609,8 @@ hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
   absmax_partial<<<dim3(kAmaxBlocks, 3), 256, 0, s>>>(a);
   scales_final<<<1, 64, 0, s>>>(a, scl);
   const int rp = p.R <= 16 ? 16 : 32;
-  dim3 grid((unsigned)((p.n + kRowsWG - 1) / kRowsWG), (unsigned)p.splits);
+  const int rows = mfma_rows_per_block(p.kind, p.d, gm ? 1 : 0);
+  dim3 grid((unsigned)((p.n + rows - 1) / rows), (unsigned)p.splits);
   const int dd = p.d;
   if (dd == 1)
     launch_d<1>(a, rp, gm, grid, s);

@@ -44,9 +44,13 @@ struct PassDesc {
   void *mfma_scratch;  // scale exponents and partial maxima of the matrix-core pass
 };
 
-// Rows per block of the pair kernels (VALU and MFMA variants).
+// Rows per block of the pair kernels (VALU and MFMA variants).  The matrix-core kernel uses
+// 256 rows, or 128 for the per-coordinate gradient at d >= 8; workspaces are sized for the
+// smaller block.
 constexpr int kRowsValu = kThreads;
 constexpr int kRowsMfma = 256;
+constexpr int kRowsMfmaMin = 128;
+int mfma_rows_per_block(int kind, int d, int has_grad);
 
 int64_t pair_blocks(const PassDesc &p);
 int64_t fin_blocks(const PassDesc &p);

@@ -13,8 +13,9 @@ Workloads (shapes and distributions of the five benchmark configurations):
   large3      N=2^20, X ~ U[0,1]^3, isotropic SE, l = 0.05, alpha = 1, sigma^2 = 1e-3;
               32 N(0,1) auxiliary vectors.
   batched     64 instances, N_b uniform integers in [2048, 32768], d_b in {4, 8, 16},
-              X ~ N(0, I_d), ARD SE, l_k log-uniform on [0.3, 3], alpha = 1, sigma^2 = 1e-2,
-              y = prod_k cos(x_k) + 0.1 N(0,1); 8 chains each; 20-step trajectories.
+              X ~ N(0, I_d), ARD SE, l_k log-uniform on [0.3, 3], alpha = 1, sigma^2 = 0.1 (the
+              noise variance of the paper's synthetic scaling runs), y = prod_k cos(x_k) +
+              0.1 N(0,1); 8 chains each; 20-step trajectories.
   ard64       N=262,144, X ~ N(0, I_64), ARD SE, l_k log-uniform on [0.5, 8], alpha = 1,
               sigma^2 = 1e-2; 16 chains x 50 leapfrog steps.
 """
@@ -93,7 +94,7 @@ def large3(n=1 << 20, r=32):
     }
 
 
-def batched(n_inst=64, chains=8, n_lo=2048, n_hi=32768, dims=(4, 8, 16), n_steps=20):
+def batched(n_inst=64, chains=8, n_lo=2048, n_hi=32768, dims=(4, 8, 16), n_steps=20, sigma2=0.1):
     s = WORKLOAD_SEEDS["batched"]
     g = rng(s, P_SHAPE)
     ns = g.integers(n_lo, n_hi, endpoint=True, size=n_inst)
@@ -102,7 +103,7 @@ def batched(n_inst=64, chains=8, n_lo=2048, n_hi=32768, dims=(4, 8, 16), n_steps
     for b in range(n_inst):
         sb = 1000 + b
         X = normal_points(int(ns[b]), int(ds[b]), sb)
-        theta = theta_ard_loguniform(int(ds[b]), 0.3, 3.0, sb)
+        theta = theta_ard_loguniform(int(ds[b]), 0.3, 3.0, sb, sigma2=sigma2)
         inst.append({
             "X": X, "y": y_prodcos(X, sb), "theta": theta,
             "xi": rng(sb, P_XI).standard_normal((chains, int(ns[b]))),
