@@ -34,7 +34,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def bench_large3(steps, warmup):
+def bench_large3(steps, warmup, tune=True):
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
@@ -42,6 +42,16 @@ def bench_large3(steps, warmup):
     dev = "cuda:0"
     w = inputs.large3()
     n, r = w["X"].shape[0], w["Z"].shape[1]
+    tuned = None
+    if tune:
+        t0 = time.perf_counter()
+        gpk.tune("iso", 3, n, r, torch.float32, with_grad=True)
+        path = os.path.join(ROOT, "gpurun_out", "tune_large3.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+        tuned = {"seconds": time.perf_counter() - t0}
+        if path:
+            gpk.tune_save(path)
+            tuned["table"] = path
+        log(f"tuned in {tuned['seconds']:.1f} s")
     X = torch.tensor(w["X"], dtype=torch.float32, device=dev)
     Z = torch.tensor(w["Z"], dtype=torch.float32, device=dev)
     th = torch.tensor(w["theta"], dtype=torch.float64, device=dev)
@@ -65,7 +75,7 @@ def bench_large3(steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev]
-    return {"w": w, "res": res, "wall": wall, "per_call": per, "n": n, "r": r}
+    return {"w": w, "res": res, "wall": wall, "per_call": per, "n": n, "r": r, "tuned": tuned}
 
 
 def parity_sample(b, n_rows=6):
@@ -228,6 +238,7 @@ def main():
     ap.add_argument("--leapfrog-modes", default="graph,plain")
     ap.add_argument("--leapfrog-subset", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
@@ -242,7 +253,7 @@ def main():
     if args.copy_calibration:
         log(f"copy calibration: {copy_calibration()}")
     log("large3: generating inputs and warming up")
-    b = bench_large3(args.steps, args.warmup)
+    b = bench_large3(args.steps, args.warmup, tune=not args.no_tune)
     n = b["n"]
     t_step = float(np.median(b["per_call"]))
     value = n * n * args.steps / b["wall"]
@@ -265,6 +276,7 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR,
                      "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR},
         "parity": par,
+        "autotune": b["tuned"],
     }
     if not args.no_cpu:
         log("cpu baseline: timing the FP64 oracle on a row slab")

@@ -136,6 +136,25 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
                            int64_t ldau, void *AV, int64_t ldav, void *ws, size_t ws_bytes,
                            hipStream_t stream);
 
+/*
+ * Autotuning of the product kernels.  For the problem class of (k, n, r) -- operation
+ * (with_grad: gp_quadform_grad, else gp_kmatvec), precision, kernel kind, padded d, padded r and
+ * floor(log2 n) -- gp_tune_products times every candidate configuration (column splits of the
+ * pair grid; rows per wavefront of the matrix-core kernel) on synthetic inputs it generates in
+ * `ws` (at least gp_tune_workspace_size bytes) and records the fastest in a process-wide table
+ * that later calls of that class use.  The call synchronises `stream`.  Results of a product do
+ * not depend on the configuration beyond the order of its floating-point sums.
+ * gp_tune_save / gp_tune_load write / read the table as JSON; if the environment variable
+ * GPK_TUNE_CACHE names a file, it is loaded on first use.
+ */
+size_t gp_tune_workspace_size(const gp_kernel *k, int64_t n, int32_t r);
+gp_status gp_tune_products(const gp_kernel *k, int64_t n, int32_t r, int32_t with_grad,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+gp_status gp_tune_save(const char *path);
+gp_status gp_tune_load(const char *path);
+int32_t gp_tune_entries(void);
+void gp_tune_clear(void);
+
 /* Trajectory parameters. */
 typedef struct {
   int32_t n_steps;  /* leapfrog steps per trajectory, N_int >= 0 */

@@ -6,6 +6,7 @@
 
 #include "gpk.h"
 #include "pass.h"
+#include "tune.h"
 
 namespace gpk {
 
@@ -53,7 +54,7 @@ hipError_t zero_doubles(double *a, int64_t m, hipStream_t s) {
 }
 
 int64_t pair_blocks(const PassDesc &p) {
-  const int rows = p.use_mfma ? mfma_rows_per_block(p.kind, p.d, p.P ? 1 : 0) : kRowsValu;
+  const int rows = p.use_mfma ? mfma_rows_per_block(p.kind, p.d, p.P ? 1 : 0, p.ib) : kRowsValu;
   return ((p.n + rows - 1) / rows) * p.splits;
 }
 
@@ -112,24 +113,54 @@ struct Plan {
   int dp;
   int rpass;
   int splits;
+  int max_splits;
+  int ib;
   int use_mfma;
   int nrec;
   WsLayout L;
 };
 
-static Plan make_plan(const gp_kernel *k, int64_t n, int r) {
+// Largest column-split count a workspace is sized for: at most 64, at least 2048 columns per
+// split, and at most 1 GiB of split partials.
+static int max_splits_for(int64_t n, int rpass) {
+  int64_t m = 64;
+  if (n / 2048 < m) m = n / 2048;
+  const int64_t cap = ((int64_t)1 << 30) / (8 * n * (int64_t)rpass);
+  if (cap < m) m = cap;
+  return m < 1 ? 1 : (int)m;
+}
+
+static thread_local bool t_forced = false;
+static thread_local TuneCfg t_force_cfg;
+
+static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
   Plan pl;
   pl.dp = padded_dim(k->d);
   pl.rpass = r < kMaxRPass ? r : kMaxRPass;
   if (pl.rpass < 1) pl.rpass = 1;
   pl.use_mfma = mfma_supported(k->prec, k->kind, k->d, pl.rpass) ? 1 : 0;
   const int rows = pl.use_mfma ? kRowsMfma : kRowsValu;
+  pl.max_splits = max_splits_for(n, pl.rpass);
   pl.splits = choose_splits(n, rows);
+  if (pl.splits > pl.max_splits) pl.splits = pl.max_splits;
+  pl.ib = 2;
+  TuneCfg c;
+  bool have = false;
+  if (t_forced) {
+    c = t_force_cfg;
+    have = true;
+  } else if (op >= 0) {
+    have = tune_lookup(tune_key(op, k->prec, k->kind, k->d, pl.rpass, n), &c);
+  }
+  if (have) {
+    pl.splits = c.splits < 1 ? 1 : (c.splits > pl.max_splits ? pl.max_splits : c.splits);
+    pl.ib = c.ib == 1 ? 1 : 2;
+  }
   pl.nrec = nth_of(k) + pl.rpass;
   const int rows_min = pl.use_mfma ? kRowsMfmaMin : kRowsValu;
-  const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.splits;
-  const int64_t fb = pl.splits > 1 ? (n + kThreads - 1) / kThreads : 0;
-  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.splits, pb, fb, pl.nrec,
+  const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.max_splits;
+  const int64_t fb = pl.max_splits > 1 ? (n + kThreads - 1) / kThreads : 0;
+  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec,
                    pl.use_mfma ? mfma_scratch_bytes() : 0);
   return pl;
 }
@@ -152,7 +183,29 @@ static PassDesc base_desc(const gp_kernel *k, const Plan &pl, int64_t n, const d
   p.nth = nth_of(k);
   p.use_mfma = pl.use_mfma;
   p.mfma_scratch = ws + pl.L.scratch;
+  p.ib = pl.ib;
   return p;
+}
+
+void tune_force(const TuneCfg *c) {
+  t_forced = c != nullptr;
+  if (c) t_force_cfg = *c;
+}
+
+std::vector<TuneCfg> tune_candidates(const gp_kernel *k, int64_t n, int r, int with_grad) {
+  const Plan pl = make_plan(k, n, r, -1);
+  std::vector<TuneCfg> out;
+  const bool two = pl.use_mfma && mfma_ib(k->kind, k->d, with_grad, 2) == 2;
+  for (int s = 1; s <= pl.max_splits; s *= 2) {
+    for (int ib = two ? 1 : 2; ib <= 2; ++ib) {
+      TuneCfg c;
+      c.splits = s;
+      c.ib = ib;
+      c.ms = 0.f;
+      out.push_back(c);
+    }
+  }
+  return out;
 }
 
 }  // namespace gpk
@@ -184,7 +237,7 @@ size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
   if (check_kernel(k, true) != GP_OK || n < 0 || r < 0) return 0;
   if (n == 0 || r == 0) return 0;
   if (k->prec == GP_BF16X) return 0;
-  return make_plan(k, n, r).L.total;
+  return make_plan(k, n, r, -1).L.total;
 }
 
 gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double *theta,
@@ -204,7 +257,7 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
                 (long long)ldv, (long long)ldo, r);
   const size_t es = elem_size(k->prec);
   if (overlap(V, n, ldv, r, out, n, ldo, r, es)) return fail(GP_ERR_ARG, "out overlaps V");
-  const Plan pl = make_plan(k, n, r);
+  const Plan pl = make_plan(k, n, r, 0);
   if (!ws || ws_bytes < pl.L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -261,7 +314,7 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
       overlap(AV, n, ldav, r, U, n, ldu, r, es) || overlap(AV, n, ldav, r, V, n, ldv, r, es) ||
       overlap(AU, n, ldau, r, AV, n, ldav, r, es))
     return fail(GP_ERR_ARG, "an output overlaps an input or the other output");
-  const Plan pl = make_plan(k, n, r);
+  const Plan pl = make_plan(k, n, r, 1);
   if (!ws || ws_bytes < pl.L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
                 ws ? ws_bytes : (size_t)0);

@@ -32,9 +32,11 @@ namespace mf {
 
 constexpr int kWaves = 8;
 constexpr int kWG = kWaves * 64;  // 512 threads
-constexpr int TJ = 32;            // columns per tile
+constexpr int TH = 32;            // columns per MFMA half-tile
+constexpr int NHALF = 2;          // half-tiles per LDS tile (one barrier interval)
+constexpr int TJ = TH * NHALF;    // columns per LDS tile
 constexpr int kStrideH = 40;      // halves per LDS row of the split tiles (80 bytes)
-constexpr int kFold = 8;          // tiles between folds of the float partials
+constexpr int kFold = 4;          // tiles (of 64 columns) between folds of the float partials
 constexpr int kScaleTop = 14;     // operands scaled below 2^14
 constexpr int kAmaxBlocks = 64;
 
@@ -138,11 +140,10 @@ __global__ void scales_final(MArgs a, int *scl) {
 
 // GM: 0 product only, 1 isotropic gradient, 2 per-coordinate gradient.
 // D: coordinates used (1..4 stored with stride 4, or 8, 16).  RP: padded R (16 or 32).
-template <int D, int RP, int GM>
+// IB: 16-row blocks per wave (1 or 2; the per-coordinate gradient at d >= 8 always uses 1,
+// its accumulators need the registers of the second block).
+template <int D, int RP, int GM, int IB>
 __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
-  // 16-row blocks per wave: two, except for the per-coordinate gradient at d >= 8, whose
-  // accumulators need the registers of the second block
-  constexpr int IB = (GM == 2 && D >= 8) ? 1 : 2;
   constexpr int kRowsWG = kWaves * IB * 16;
   constexpr int XS = D <= 4 ? 4 : D;         // LDS/global stride of a point
   constexpr int NCB = RP / 16;               // 16-column blocks of the product
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   __shared__ float sx[2][TJ * XS];
   __shared__ __attribute__((aligned(16))) _Float16 sqh[2][TJ * kStrideH];   // Q[j][c]
   __shared__ __attribute__((aligned(16))) _Float16 sql[2][TJ * kStrideH];
-  __shared__ __attribute__((aligned(16))) _Float16 syh[2][RP * kStrideH];   // Y^T[c][slot]
-  __shared__ __attribute__((aligned(16))) _Float16 syl[2][RP * kStrideH];
+  __shared__ __attribute__((aligned(16))) _Float16 syh[2][NHALF * RP * kStrideH];  // Y^T[h][c][slot]
+  __shared__ __attribute__((aligned(16))) _Float16 syl[2][NHALF * RP * kStrideH];
   __shared__ double shr[kWaves][4];
 
   const int tid = threadIdx.x;
@@ -224,43 +225,58 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   const int ntiles = (int)((j1 - j0 + TJ - 1) / TJ);
   const bool sym = (a.Y == a.Q && a.ldy == a.ldq);
 
-  // Column tiles are software-pipelined: the global loads of tile t + 2 are issued before the
-  // compute of tile t + 1 and land in registers; after the compute of tile t the registers of
-  // tile t + 1 are split and written to the other LDS buffer.  Out-of-range columns are zero
-  // in Y and Q and their coordinates are pushed far away so their kernel values vanish.
+  // Column tiles (64 columns = two 32-column MFMA halves) are software-pipelined: the global
+  // loads of tile t + 2 are issued after the compute of tile t and land in registers; the
+  // registers of tile t + 1 are split and written to the other LDS buffer after the compute of
+  // tile t.  Out-of-range columns are zero in Y and Q and their coordinates are pushed far
+  // away so their kernel values vanish.
   constexpr int NE = (TJ * RP + kWG - 1) / kWG;  // Y/Q elements per thread per tile
   constexpr int NX = TJ * XS;                     // coordinate elements per tile
-  float ry[NE], rq[NE], rx = 0.0f;
+  constexpr int NXT = (NX + kWG - 1) / kWG;
+  float ry[NE], rq[NE], rx[NXT];
+  // per-thread element positions are the same in every tile: offsets advance by TJ rows
+  int e_jj[NE], e_c[NE];
+  int64_t oy[NE], oq[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * kWG;
+    e_jj[u] = e / RP;
+    e_c[u] = e - e_jj[u] * RP;
+    oy[u] = (j0 + e_jj[u]) * a.ldy + e_c[u];
+    oq[u] = (j0 + e_jj[u]) * a.ldq + e_c[u];
+  }
+  const int64_t step_y = (int64_t)TJ * a.ldy, step_q = (int64_t)TJ * a.ldq;
   auto prefetch = [&](int t) {
     const int64_t jt = j0 + (int64_t)t * TJ;
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kWG;
-      const int jj = e / RP, c = e - jj * RP;
-      const int64_t j = jt + jj;
-      const bool ok = e < TJ * RP && j < j1 && c < R;
-      ry[u] = ok ? a.Y[j * a.ldy + c] : 0.0f;
-      if (GM && !sym) rq[u] = ok ? a.Q[j * a.ldq + c] : 0.0f;
+      const bool ok = (tid + u * kWG) < TJ * RP && jt + e_jj[u] < j1 && e_c[u] < R;
+      ry[u] = ok ? a.Y[oy[u] + t * step_y] : 0.0f;
+      if (GM && !sym) rq[u] = ok ? a.Q[oq[u] + t * step_q] : 0.0f;
     }
-    if (tid < NX) {
-      const int jj = tid / XS, k = tid - jj * XS;
-      const int64_t j = jt + jj;
-      rx = j < j1 ? a.xs[j * XS + k] : (k == 0 ? 1.0e18f : 0.0f);
+#pragma unroll
+    for (int u = 0; u < NXT; ++u) {
+      const int e = tid + u * kWG;
+      if (e < NX) {
+        const int jj = e / XS, k = e - jj * XS;
+        const int64_t j = jt + jj;
+        rx[u] = j < j1 ? a.xs[j * XS + k] : (k == 0 ? 1.0e18f : 0.0f);
+      }
     }
   };
   auto commit = [&](int b) {
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kWG;
-      if (e < TJ * RP) {
-        const int jj = e / RP, c = e - jj * RP;
+      if ((tid + u * kWG) < TJ * RP) {
+        const int jj = e_jj[u], c = e_c[u];
+        const int hh = jj >> 5, jl = jj & 31;
         float h, l;
         split(ry[u] * sY, h, l);
-        // slot of column jj in the transposed product operand
-        const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
+        // slot of column jl of half hh in the transposed product operand
+        const int gg = (jl & 15) >> 2, q = 4 * (jl >> 4) + (jl & 3);
         const int slot = 8 * gg + q;
-        syh[b][c * kStrideH + slot] = (_Float16)h;
-        syl[b][c * kStrideH + slot] = (_Float16)l;
+        syh[b][(hh * RP + c) * kStrideH + slot] = (_Float16)h;
+        syl[b][(hh * RP + c) * kStrideH + slot] = (_Float16)l;
         if (GM) {
           float qh, ql;
           split((sym ? ry[u] : rq[u]) * sQ, qh, ql);
@@ -269,7 +285,11 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
         }
       }
     }
-    if (tid < NX) sx[b][tid] = rx;
+#pragma unroll
+    for (int u = 0; u < NXT; ++u) {
+      const int e = tid + u * kWG;
+      if (e < NX) sx[b][e] = rx[u];
+    }
   };
   if (GM && RP < 32) {
     // the unused half of the S contraction (c = RP .. 31) stays zero in both buffers
@@ -290,89 +310,91 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     const int b = t & 1;
-    // ---- S^T for both 16-column halves and all row blocks -------------------------------
-    f32x4 s[IB][2];
-    if (GM) {
+#pragma unroll 1
+    for (int hf = 0; hf < NHALF; ++hf) {
+      // ---- S^T for both 16-column quarters of this half and all row blocks ---------------
+      f32x4 s[IB][2];
+      if (GM) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          H8 vh, vl;
+          const int row = 32 * hf + 16 * jb + m;
+          vh.v = *(const f16x8 *)&sqh[b][row * kStrideH + 8 * g];
+          vl.v = *(const f16x8 *)&sql[b][row * kStrideH + 8 * g];
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib) {
+            f32x4 z = {0.f, 0.f, 0.f, 0.f};
+            z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, ph[ib].v, z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, pl[ib].v, z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vl.v, ph[ib].v, z, 0, 0, 0);
+            s[ib][jb] = z;
+          }
+        }
+      }
+      // ---- kernel values (VALU) into the A operand of the product -------------------------
+      H8 kh[IB], kl[IB];
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
-        H8 vh, vl;
-        const _Float16 *ph_ = &sqh[b][(16 * jb + m) * kStrideH + 8 * g];
-        const _Float16 *pl_ = &sql[b][(16 * jb + m) * kStrideH + 8 * g];
-        vh.v = *(const f16x8 *)ph_;
-        vl.v = *(const f16x8 *)pl_;
+        float kv[IB][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float xj[D];
+          const float *p0 = &sx[b][(32 * hf + 16 * jb + 4 * g + r) * XS];
+#pragma unroll
+          for (int k = 0; k < D; ++k) xj[k] = p0[k];
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib) {
+            float d2[GM == 2 ? D : 1];
+            float rho = 0.f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+              const float u = xi[ib][k] - xj[k];
+              if (GM == 2) {
+                d2[k] = u * u;
+                rho += d2[k];
+              } else {
+                rho = fmaf(u, u, rho);
+              }
+            }
+            const float kk = __builtin_amdgcn_exp2f(c0 - rho);
+            if (GM) {
+              const float W = kk * s[ib][jb][r];
+              if (GM == 1) {
+                gl[0] = fmaf(W, rho, gl[0]);
+              } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) gl[k] = fmaf(W, d2[k], gl[k]);
+              }
+            }
+            kv[ib][r] = kk;
+          }
+        }
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
-          f32x4 z = {0.f, 0.f, 0.f, 0.f};
-          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, ph[ib].v, z, 0, 0, 0);
-          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, pl[ib].v, z, 0, 0, 0);
-          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vl.v, ph[ib].v, z, 0, 0, 0);
-          s[ib][jb] = z;
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            float h0, l0, h1, l1;
+            split(kv[ib][r], h0, l0);
+            split(kv[ib][r + 1], h1, l1);
+            kh[ib].u[2 * jb + r / 2] = pk_rtz(h0, h1);
+            kl[ib].u[2 * jb + r / 2] = pk_rtz(l0, l1);
+          }
         }
       }
-    }
-    // ---- kernel values (VALU) into the A operand of the product ---------------------------
-    H8 kh[IB], kl[IB];
+      // ---- product out += K Y -------------------------------------------------------------
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      float kv[IB][4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float xj[D];
-        const float *p0 = &sx[b][(16 * jb + 4 * g + r) * XS];
-#pragma unroll
-        for (int k = 0; k < D; ++k) xj[k] = p0[k];
+      for (int cb = 0; cb < NCB; ++cb) {
+        H8 yh, yl;
+        yh.v = *(const f16x8 *)&syh[b][(hf * RP + 16 * cb + m) * kStrideH + 8 * g];
+        yl.v = *(const f16x8 *)&syl[b][(hf * RP + 16 * cb + m) * kStrideH + 8 * g];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
-          float d2[GM == 2 ? D : 1];
-          float rho = 0.f;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const float u = xi[ib][k] - xj[k];
-            if (GM == 2) {
-              d2[k] = u * u;
-              rho += d2[k];
-            } else {
-              rho = fmaf(u, u, rho);
-            }
-          }
-          const float kk = __builtin_amdgcn_exp2f(c0 - rho);
-          if (GM) {
-            const float W = kk * s[ib][jb][r];
-            if (GM == 1) {
-              gl[0] = fmaf(W, rho, gl[0]);
-            } else {
-#pragma unroll
-              for (int k = 0; k < D; ++k) gl[k] = fmaf(W, d2[k], gl[k]);
-            }
-          }
-          kv[ib][r] = kk;
+          f32x4 z = acc[ib][cb];
+          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yh.v, z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yl.v, z, 0, 0, 0);
+          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl[ib].v, yh.v, z, 0, 0, 0);
+          acc[ib][cb] = z;
         }
-      }
-#pragma unroll
-      for (int ib = 0; ib < IB; ++ib) {
-#pragma unroll
-        for (int r = 0; r < 4; r += 2) {
-          float h0, l0, h1, l1;
-          split(kv[ib][r], h0, l0);
-          split(kv[ib][r + 1], h1, l1);
-          kh[ib].u[2 * jb + r / 2] = pk_rtz(h0, h1);
-          kl[ib].u[2 * jb + r / 2] = pk_rtz(l0, l1);
-        }
-      }
-    }
-    // ---- product out += K Y ---------------------------------------------------------------
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      H8 yh, yl;
-      yh.v = *(const f16x8 *)&syh[b][(16 * cb + m) * kStrideH + 8 * g];
-      yl.v = *(const f16x8 *)&syl[b][(16 * cb + m) * kStrideH + 8 * g];
-#pragma unroll
-      for (int ib = 0; ib < IB; ++ib) {
-        f32x4 z = acc[ib][cb];
-        z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yh.v, z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yl.v, z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl[ib].v, yh.v, z, 0, 0, 0);
-        acc[ib][cb] = z;
       }
     }
     if (t + 1 < ntiles) commit(b ^ 1);
@@ -537,31 +559,47 @@ __global__ __launch_bounds__(256) void finalise_mfma(MArgs a, int has_grad) {
   }
 }
 
+template <int D, int RP, int GM>
+static void launch_d_rp_gm(const MArgs &ma, int ib, dim3 grid, hipStream_t s) {
+  if constexpr (GM == 2 && D >= 8) {
+    pair_mfma<D, RP, GM, 1><<<grid, kWG, 0, s>>>(ma);
+  } else {
+    if (ib == 1)
+      pair_mfma<D, RP, GM, 1><<<grid, kWG, 0, s>>>(ma);
+    else
+      pair_mfma<D, RP, GM, 2><<<grid, kWG, 0, s>>>(ma);
+  }
+}
+
 template <int D, int RP>
-static void launch_d_rp(const MArgs &ma, int gm, dim3 grid, hipStream_t s) {
+static void launch_d_rp(const MArgs &ma, int gm, int ib, dim3 grid, hipStream_t s) {
   if (gm == 0)
-    pair_mfma<D, RP, 0><<<grid, kWG, 0, s>>>(ma);
+    launch_d_rp_gm<D, RP, 0>(ma, ib, grid, s);
   else if (gm == 1)
-    pair_mfma<D, RP, 1><<<grid, kWG, 0, s>>>(ma);
+    launch_d_rp_gm<D, RP, 1>(ma, ib, grid, s);
   else
-    pair_mfma<D, RP, 2><<<grid, kWG, 0, s>>>(ma);
+    launch_d_rp_gm<D, RP, 2>(ma, ib, grid, s);
 }
 
 }  // namespace mf
 
-int mfma_rows_per_block(int kind, int d, int has_grad) {
-  const int dd = d <= 4 ? d : (d <= 8 ? 8 : 16);
-  return (has_grad && kind != 0 && dd >= 8) ? mf::kWaves * 16 : mf::kWaves * 32;
+int mfma_ib(int kind, int d, int has_grad, int ib_request) {
+  if (has_grad && kind != 0 && d > 4) return 1;
+  return ib_request == 1 ? 1 : 2;
+}
+
+int mfma_rows_per_block(int kind, int d, int has_grad, int ib_request) {
+  return mf::kWaves * 16 * mfma_ib(kind, d, has_grad, ib_request);
 }
 
 namespace mf {
 
 template <int D>
-static void launch_d(const MArgs &ma, int rp, int gm, dim3 grid, hipStream_t s) {
+static void launch_d(const MArgs &ma, int rp, int gm, int ib, dim3 grid, hipStream_t s) {
   if (rp == 16)
-    launch_d_rp<D, 16>(ma, gm, grid, s);
+    launch_d_rp<D, 16>(ma, gm, ib, grid, s);
   else
-    launch_d_rp<D, 32>(ma, gm, grid, s);
+    launch_d_rp<D, 32>(ma, gm, ib, grid, s);
 }
 
 }  // namespace mf
@@ -609,21 +647,22 @@ hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
   absmax_partial<<<dim3(kAmaxBlocks, 3), 256, 0, s>>>(a);
   scales_final<<<1, 64, 0, s>>>(a, scl);
   const int rp = p.R <= 16 ? 16 : 32;
-  const int rows = mfma_rows_per_block(p.kind, p.d, gm ? 1 : 0);
+  const int ib = mfma_ib(p.kind, p.d, gm ? 1 : 0, p.ib);
+  const int rows = mfma_rows_per_block(p.kind, p.d, gm ? 1 : 0, p.ib);
   dim3 grid((unsigned)((p.n + rows - 1) / rows), (unsigned)p.splits);
   const int dd = p.d;
   if (dd == 1)
-    launch_d<1>(a, rp, gm, grid, s);
+    launch_d<1>(a, rp, gm, ib, grid, s);
   else if (dd == 2)
-    launch_d<2>(a, rp, gm, grid, s);
+    launch_d<2>(a, rp, gm, ib, grid, s);
   else if (dd == 3)
-    launch_d<3>(a, rp, gm, grid, s);
+    launch_d<3>(a, rp, gm, ib, grid, s);
   else if (dd == 4)
-    launch_d<4>(a, rp, gm, grid, s);
+    launch_d<4>(a, rp, gm, ib, grid, s);
   else if (dd <= 8)
-    launch_d<8>(a, rp, gm, grid, s);
+    launch_d<8>(a, rp, gm, ib, grid, s);
   else
-    launch_d<16>(a, rp, gm, grid, s);
+    launch_d<16>(a, rp, gm, ib, grid, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p.splits > 1) {

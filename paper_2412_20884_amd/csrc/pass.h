@@ -42,6 +42,7 @@ struct PassDesc {
   int nrec;
   int use_mfma;  // 1: the matrix-core pair kernel (float, 8 <= R <= 32, d <= 16)
   void *mfma_scratch;  // scale exponents and partial maxima of the matrix-core pass
+  int ib;              // matrix-core kernel: 16-row blocks per wave requested (1 or 2)
 };
 
 // Rows per block of the pair kernels (VALU and MFMA variants).  The matrix-core kernel uses
@@ -50,7 +51,8 @@ struct PassDesc {
 constexpr int kRowsValu = kThreads;
 constexpr int kRowsMfma = 256;
 constexpr int kRowsMfmaMin = 128;
-int mfma_rows_per_block(int kind, int d, int has_grad);
+int mfma_rows_per_block(int kind, int d, int has_grad, int ib_request);
+int mfma_ib(int kind, int d, int has_grad, int ib_request);
 
 int64_t pair_blocks(const PassDesc &p);
 int64_t fin_blocks(const PassDesc &p);

@@ -22,7 +22,8 @@ CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED = 1, 2, 
 
 EXPORTED = (
     "gp_last_error", "gp_status_string", "gp_n_theta", "gp_workspace_size", "gp_kmatvec",
-    "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog",
+    "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog", "gp_tune_workspace_size",
+    "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
 )
 
 
@@ -85,6 +86,18 @@ def lib():
     L.gp_hmc_leapfrog.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
                                   ctypes.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gp_tune_workspace_size.restype = _sz
+    L.gp_tune_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32]
+    L.gp_tune_products.restype = _i32
+    L.gp_tune_products.argtypes = [ctypes.POINTER(Kernel), _i64, _i32, _i32, _vp, _sz, _vp]
+    L.gp_tune_save.restype = _i32
+    L.gp_tune_save.argtypes = [ctypes.c_char_p]
+    L.gp_tune_load.restype = _i32
+    L.gp_tune_load.argtypes = [ctypes.c_char_p]
+    L.gp_tune_entries.restype = _i32
+    L.gp_tune_entries.argtypes = []
+    L.gp_tune_clear.restype = None
+    L.gp_tune_clear.argtypes = []
     _LIB = L
     return L
 
@@ -260,3 +273,31 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
                                  _p(phi), _p(theta), _p(pi), _p(x_warm), _p(u), _p(H0), _p(H1),
                                  _p(acc), _p(st), _p(it), _p(ws), ws.numel(), _stream(dev)))
     return {"H0": H0, "H1": H1, "accepted": acc, "status": st, "cg_iters": it}
+
+
+def tune(kind, d, n, r, dtype=torch.float32, with_grad=True, device="cuda:0", prec=None):
+    """Autotune the product kernels for this problem class (synthetic inputs on `device`)."""
+    k = Kernel(kind_code(kind), prec_code(dtype, prec), int(d), 0)
+    nbytes = int(lib().gp_tune_workspace_size(ctypes.byref(k), int(n), int(r)))
+    if nbytes == 0:
+        raise ValueError("no product kernels for this description")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _check(lib().gp_tune_products(ctypes.byref(k), int(n), int(r), 1 if with_grad else 0, _p(ws),
+                                  nbytes, _stream(torch.device(device))))
+    return int(lib().gp_tune_entries())
+
+
+def tune_save(path):
+    _check(lib().gp_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    _check(lib().gp_tune_load(str(path).encode()))
+
+
+def tune_entries():
+    return int(lib().gp_tune_entries())
+
+
+def tune_clear():
+    lib().gp_tune_clear()

@@ -95,3 +95,27 @@ def test_workspace_size_monotone():
     assert 0 < a < b
     assert L.gp_workspace_size(k, 0, 4) == 0
     assert L.gp_workspace_size(None, 10, 4) == 0
+
+
+def test_tune_table_json_roundtrip(tmp_path):
+    # the tuning table loads from and saves to JSON without a GPU
+    gpk.tune_clear()
+    src = tmp_path / "in.json"
+    src.write_text('{"version": 1, "entries": [\n'
+                   ' {"op": 1, "prec": 1, "kind": 0, "dp": 4, "rb": 32, "nb": 20, "splits": 2, "ib": 2, "ms": 780.5},\n'
+                   ' {"op": 0, "prec": 0, "kind": 1, "dp": 8, "rb": 1, "nb": 12, "splits": 8, "ib": 1, "ms": 0.25},\n'
+                   ' {"op": 0, "prec": 0, "kind": 1, "dp": 8, "rb": 1, "nb": 13, "splits": 0, "ib": 1, "ms": 0.25}\n'
+                   ']}\n')
+    gpk.tune_load(src)
+    assert gpk.tune_entries() == 2          # the entry with splits = 0 is rejected
+    out = tmp_path / "out.json"
+    gpk.tune_save(out)
+    gpk.tune_clear()
+    assert gpk.tune_entries() == 0
+    gpk.tune_load(out)
+    assert gpk.tune_entries() == 2
+    text = out.read_text()
+    assert '"splits": 2' in text and '"nb": 12' in text
+    gpk.tune_clear()
+    L = gpk.lib()
+    assert L.gp_tune_load(b"/nonexistent/x.json") == 1

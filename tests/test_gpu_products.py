@@ -215,3 +215,26 @@ def test_mfma_operand_scaling(mag, log_alpha):
     assert col_rel_err(host(out), ref["AV"]) < 1e-5
     scale = _grad_scale(X, th, "iso", V, V, np.ones(16))
     assert grad_rel_err(host(res["grad"]), ref["grad"], scale) < 1e-5
+
+
+@pytest.mark.parametrize("kind,d,r", [("iso", 3, 32), ("ard", 8, 16), ("iso", 2, 1)])
+def test_autotuned_config_keeps_parity(kind, d, r):
+    """After tuning a problem class the products still match the oracle."""
+    n = 4500
+    gpk.tune_clear()
+    gpk.tune(kind, d, n, r, torch.float32, with_grad=True)
+    gpk.tune(kind, d, n, r, torch.float32, with_grad=False)
+    assert gpk.tune_entries() == 2
+    p = _problem(kind, n, d, 61 + d, r)
+    X, U = rounded(p["X"], torch.float32), rounded(p["U"], torch.float32)
+    th = p["theta"]
+    Ud = to_dev(U, torch.float32)
+    res = gpk.quadform_grad(to_dev(X, torch.float32), to_dev(th, torch.float64), Ud, Ud, None, kind,
+                            want_AU=True)
+    out = gpk.kmatvec(to_dev(X, torch.float32), to_dev(th, torch.float64), Ud, kind)
+    torch.cuda.synchronize()
+    gpk.tune_clear()
+    ref = ogp.quadform_grad(X, th, kind, U, U)
+    assert col_rel_err(host(res["AU"]), ref["AU"]) < 1e-5
+    assert col_rel_err(host(out), ref["AU"]) < 1e-5
+    assert grad_rel_err(host(res["grad"]), ref["grad"], _grad_scale(X, th, kind, U, U, np.ones(r))) < 1e-5
