@@ -219,6 +219,58 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
                           double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Gibbs refresh of phi (Section 3.1): given theta, phi | theta ~ N(0, A^{-1}) is drawn as
+ * phi = A^{-1/2} xi with xi ~ N(0, I) supplied by the caller, through the pole expansion
+ * A^{-1/2} ~ sum_p w_p (A + lambda_p I)^{-1} (eq. pex) with the weights and shifts of
+ * Appendix A (eq. msqdisc) on the spectral interval [m, M].
+ *
+ * gp_pole_weights -- host only (no GPU use): the n_poles weights w[j] and shifts shift[j] >= 0 for
+ * 0 < m <= M.  K(1 - k^2), k^2 = m / M, and the Jacobi functions at the imaginary nodes come from
+ * the arithmetic-geometric mean; Jacobi's imaginary transformation makes every node real.
+ * The approximation error of the expansion on [m, M] decays like exp(-2 pi K(k^2) N_p / K(1-k^2)).
+ */
+gp_status gp_pole_weights(double m, double M, int32_t n_poles, double *w, double *shift);
+
+enum {
+  GP_PHI_CG_MAXIT = 1,  /* some shifted system had not reached tol after maxit iterations */
+  GP_PHI_NONFINITE = 2  /* a NaN or infinity appeared (or A p . p <= 0): phi is not usable */
+};
+
+typedef struct {
+  int32_t n_poles;    /* N_p, 1..64 (15 gives ~1e-11 relative accuracy at condition 1e4) */
+  double tol;         /* relative residual |xi - (A + lambda_p I) x_p| / |xi| of every pole, > 0 */
+  int32_t maxit;      /* iteration limit, >= 1 */
+  double lambda_max;  /* M >= lambda_max(A); <= 0: the Gershgorin bound max_i (A 1)_i is used */
+} gp_phi_params;
+
+/* Bytes of workspace gp_phi_refresh needs; 0 for an invalid description or n = 0. */
+size_t gp_phi_workspace_size(const gp_kernel *k, const gp_phi_params *p, int64_t n, int32_t r);
+
+/*
+ * gp_phi_refresh -- phi = A(theta)^{-1/2} xi for r right-hand sides at once.
+ *
+ * The lower spectral bound is m = sigma^2 (read from theta).  All N_p shifted systems are solved
+ * together by multi-shift conjugate gradients on A: one product with A per iteration for every
+ * right-hand side, the shifted iterates following from the unshifted CG scalars; phi accumulates
+ * sum_p w_p x_p directly.  Iteration stops per column once every pole's residual is below tol.
+ * The host checks convergence every few iterations; the call synchronises `stream`.
+ *
+ *   X         device, n x d, kernel precision (GP_NO_NOISE is rejected: no lower bound m)
+ *   theta     device double[n_theta]
+ *   xi        device, n x r (r in 1..32), leading dimension ldxi >= r, kernel precision
+ *   phi       device out, n x r, leading dimension ldphi >= r; may be xi itself (same ld),
+ *             must not overlap it otherwise
+ *   status    device int32[r] or NULL: GP_PHI_* bits per column (0 = converged)
+ *   iters     device int32[r] or NULL: iterations used per column
+ *   bounds    host double[2] or NULL: the m and M used
+ * Vectors are kept in the kernel precision (float for GP_F32 / GP_BF16X); scalars in double.
+ */
+gp_status gp_phi_refresh(const gp_kernel *k, const gp_phi_params *p, int64_t n, const void *X,
+                         const double *theta, int32_t r, const void *xi, int64_t ldxi, void *phi,
+                         int64_t ldphi, int32_t *status, int32_t *iters, double *bounds, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,7 +54,9 @@ hipError_t zero_doubles(double *a, int64_t m, hipStream_t s) {
 }
 
 int64_t pair_blocks(const PassDesc &p) {
-  const int rows = p.use_mfma ? mfma_rows_per_block(p.kind, p.d, p.P ? 1 : 0, p.ib) : kRowsValu;
+  const int rows = p.use_mfma == 2   ? xm_rows_per_block(p.P && p.kind != 0)
+                   : p.use_mfma == 1 ? mfma_rows_per_block(p.kind, p.d, p.P ? 1 : 0, p.ib)
+                                     : kRowsValu;
   return ((p.n + rows - 1) / rows) * p.splits;
 }
 
@@ -69,6 +71,7 @@ hipError_t launch_stage(int prec, const void *X, int64_t n, int d, int dp, int k
 }
 
 hipError_t launch_pass(const PassDesc &p, hipStream_t s) {
+  if (p.use_mfma == 2) return launch_pass_xm(p, s);
   if (p.use_mfma) return launch_pass_mfma(p, s);
   if (p.prec == kF64) return launch_pass_f64(p, s);
   return launch_pass_f32(p, s);
@@ -138,7 +141,7 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
   pl.dp = padded_dim(k->d);
   pl.rpass = r < kMaxRPass ? r : kMaxRPass;
   if (pl.rpass < 1) pl.rpass = 1;
-  pl.use_mfma = mfma_supported(k->prec, k->kind, k->d, pl.rpass) ? 1 : 0;
+  pl.use_mfma = k->prec == GP_BF16X ? 2 : (mfma_supported(k->prec, k->kind, k->d, pl.rpass) ? 1 : 0);
   const int rows = pl.use_mfma ? kRowsMfma : kRowsValu;
   pl.max_splits = max_splits_for(n, pl.rpass);
   pl.splits = choose_splits(n, rows);
@@ -160,8 +163,10 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
   const int rows_min = pl.use_mfma ? kRowsMfmaMin : kRowsValu;
   const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.max_splits;
   const int64_t fb = pl.max_splits > 1 ? (n + kThreads - 1) / kThreads : 0;
-  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec,
-                   pl.use_mfma ? mfma_scratch_bytes() : 0);
+  const size_t scr = pl.use_mfma == 2 ? xm_scratch_bytes(n, k->d)
+                     : pl.use_mfma    ? mfma_scratch_bytes()
+                                      : 0;
+  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec, scr);
   return pl;
 }
 
@@ -195,7 +200,7 @@ void tune_force(const TuneCfg *c) {
 std::vector<TuneCfg> tune_candidates(const gp_kernel *k, int64_t n, int r, int with_grad) {
   const Plan pl = make_plan(k, n, r, -1);
   std::vector<TuneCfg> out;
-  const bool two = pl.use_mfma && mfma_ib(k->kind, k->d, with_grad, 2) == 2;
+  const bool two = pl.use_mfma == 1 && mfma_ib(k->kind, k->d, with_grad, 2) == 2;
   for (int s = 1; s <= pl.max_splits; s *= 2) {
     for (int ib = two ? 1 : 2; ib <= 2; ++ib) {
       TuneCfg c;
@@ -236,7 +241,6 @@ int32_t gp_n_theta(const gp_kernel *k) {
 size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
   if (check_kernel(k, true) != GP_OK || n < 0 || r < 0) return 0;
   if (n == 0 || r == 0) return 0;
-  if (k->prec == GP_BF16X) return 0;
   return make_plan(k, n, r, -1).L.total;
 }
 
@@ -246,8 +250,6 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
   clear_error();
   gp_status st = check_kernel(k, true);
   if (st) return st;
-  if (k->prec == GP_BF16X)
-    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X products are not available in this build");
   if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
   if (r < 0) return fail(GP_ERR_SHAPE, "r = %d < 0", r);
   if (n == 0 || r == 0) return GP_OK;
@@ -270,8 +272,9 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
     PassDesc p = base_desc(k, pl, n, theta, w);
     p.R = rc;
     p.nrec = nth_of(k) + rc;
-    // a narrow trailing chunk runs on the VALU kernel (same rows per block and split count)
-    p.use_mfma = mfma_supported(k->prec, k->kind, k->d, rc) ? pl.use_mfma : 0;
+    // GP_BF16X runs every chunk on its cross-term kernel; for the fp16-split kernel a narrow
+    // trailing chunk runs on the VALU kernel (same rows per block and split count)
+    p.use_mfma = pl.use_mfma == 2 ? 2 : (mfma_supported(k->prec, k->kind, k->d, rc) ? pl.use_mfma : 0);
     p.Y = (const char *)V + c0 * es;
     p.ldy = ldv;
     p.col_shift = col_shift ? col_shift + c0 : nullptr;
@@ -292,8 +295,6 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
   clear_error();
   gp_status st = check_kernel(k, false);
   if (st) return st;
-  if (k->prec == GP_BF16X)
-    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X products are not available in this build");
   if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
   if (r < 1 || r > kMaxRPass) return fail(GP_ERR_SHAPE, "r = %d outside 1..%d", r, kMaxRPass);
   if (!grad_theta && !quad && !AU && !AV)

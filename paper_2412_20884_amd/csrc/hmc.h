@@ -51,6 +51,11 @@ struct HmcChain {
   int done;
   int jobs_run;  // jobs completed in this trajectory (bounded, see HmcRunParams::max_jobs)
   double rr, yy, H0, H1;
+  // External products (GP_BF16X, plain mode): the jobs run as gp_kmatvec / gp_quadform_grad
+  // passes that write q in full, or the force and the two forms into ext_res.
+  int ext;
+  double ext_w[2];                     // (-1/2, +1/2)
+  double ext_res[kHmcMaxTheta + 2];    // gradient, then x^T A x and phi^T A phi
 };
 
 struct HmcRunParams {

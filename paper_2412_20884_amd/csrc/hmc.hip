@@ -40,7 +40,7 @@ struct InstInfo {
 };
 
 struct ChainLayout {
-  size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains;
+  size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains, prod, prod_bytes;
   std::vector<size_t> per_chain;  // offset of each chain's region
   std::vector<int> n_rb, n_cs;
   size_t total;
@@ -69,7 +69,8 @@ size_t region_bytes(const InstInfo &in, int prec, int n_cs) {
   return o;
 }
 
-ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode) {
+ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode,
+                        int kind) {
   ChainLayout L;
   const int nc = (int)inst.size() * chains;
   size_t o = 0;
@@ -84,7 +85,7 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
   L.chains = o;
   o = align256(o + chain_bytes(prec) * (size_t)nc);
   for (const InstInfo &in : inst) {
-    const int n_cs = mode == GP_HMC_PLAIN ? plain_splits(in.n) : 1;
+    const int n_cs = (mode == GP_HMC_PLAIN && prec != GP_BF16X) ? plain_splits(in.n) : 1;
     const int n_rb = (int)((in.n + kHmcTile - 1) / kHmcTile);
     for (int h = 0; h < chains; ++h) {
       L.per_chain.push_back(o);
@@ -92,6 +93,21 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
       L.n_cs.push_back(n_cs);
       o += region_bytes(in, prec, n_cs);
     }
+  }
+  L.prod = o;
+  L.prod_bytes = 0;
+  if (prec == GP_BF16X) {
+    // one product workspace, reused by every (sequentially processed) chain
+    for (const InstInfo &in : inst) {
+      gp_kernel kk;
+      kk.kind = kind;
+      kk.prec = GP_BF16X;
+      kk.d = in.d;
+      kk.flags = 0;
+      const size_t b = gp_workspace_size(&kk, in.n, 2);
+      if (b > L.prod_bytes) L.prod_bytes = b;
+    }
+    o += align256(L.prod_bytes);
   }
   L.total = o;
   return L;
@@ -101,8 +117,8 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
                   std::vector<InstInfo> &inst) {
   if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
   if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD) return fail(GP_ERR_ARG, "bad kernel kind");
-  if (k->prec != GP_F64 && k->prec != GP_F32)
-    return fail(GP_ERR_UNSUPPORTED, "gp_hmc_leapfrog runs in GP_F64 or GP_F32");
+  if (k->prec != GP_F64 && k->prec != GP_F32 && k->prec != GP_BF16X)
+    return fail(GP_ERR_ARG, "precision %d is not GP_F64, GP_F32 or GP_BF16X", k->prec);
   if (k->flags != 0) return fail(GP_ERR_ARG, "kernel flags must be 0 for gp_hmc_leapfrog");
   if (!p) return fail(GP_ERR_ARG, "params are NULL");
   if (p->n_steps < 0) return fail(GP_ERR_ARG, "n_steps < 0");
@@ -110,6 +126,8 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   if (p->cg_maxit < 1) return fail(GP_ERR_ARG, "cg_maxit must be >= 1");
   if (p->mode != GP_HMC_PLAIN && p->mode != GP_HMC_BATCHED && p->mode != GP_HMC_GRAPH)
     return fail(GP_ERR_ARG, "unknown mode %d", p->mode);
+  if (k->prec == GP_BF16X && p->mode != GP_HMC_PLAIN)
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories run in GP_HMC_PLAIN mode");
   if (!b) return fail(GP_ERR_ARG, "batch is NULL");
   if (b->n_inst < 1 || b->chains_per_inst < 1)
     return fail(GP_ERR_SHAPE, "n_inst and chains_per_inst must be >= 1");
@@ -146,7 +164,7 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const 
                  char *ws,
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
-                 int32_t *status, int32_t *iters, std::vector<HmcChain<T>> &out) {
+                 int32_t *status, int32_t *iters, int ext, std::vector<HmcChain<T>> &out) {
   out.assign(inst.size() * chains, HmcChain<T>());
   int64_t tofs = 0;
   int c = 0;
@@ -196,6 +214,7 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const 
         r += align256(sizeof(double) * ch.n_cs * n);
       }
       ch.rec = (double *)r;
+      ch.ext = ext;
     }
     tofs += in.nth;
   }
@@ -220,7 +239,7 @@ extern "C" {
 size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b) {
   std::vector<InstInfo> inst;
   if (collect(k, p, b, inst) != GP_OK) return 0;
-  return make_layout(inst, b->chains_per_inst, k->prec, p->mode).total;
+  return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind).total;
 }
 
 gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
@@ -235,7 +254,7 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status)
     return fail(GP_ERR_ARG, "X, y, phi, theta, pi, x_warm, H0, H1, accepted and status must be non-NULL");
   const int chains = b->chains_per_inst;
-  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode);
+  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind);
   if (!ws || ws_bytes < L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -246,12 +265,12 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
     fill_chains<double>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                        accepted, status, cg_iters, v);
+                        accepted, status, cg_iters, 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
     fill_chains<float>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                       accepted, status, cg_iters, v);
+                       accepted, status, cg_iters, k->prec == GP_BF16X ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
   // chain order for the batched scheduler: largest problems first
@@ -318,7 +337,33 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
         if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
         if (done) break;
         const int dpc = inst[c / chains].dp;
-        e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);
+        if (k->prec == GP_BF16X) {
+          // the job runs as one product pass of the cross-term kernel
+          int job = 0;
+          e = hipMemcpyAsync(&job, (char *)cp + off_job, sizeof(int), hipMemcpyDeviceToHost, stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(stream);
+          if (e != hipSuccess) return hip_fail(e, "plain-mode job read");
+          const InstInfo &in = inst[c / chains];
+          const HmcChain<float> *hc = (const HmcChain<float> *)desc.data() + c;
+          gp_kernel kk = *k;
+          kk.d = in.d;
+          char *pw = w + L.prod;
+          const double *thc = hc->theta;
+          gp_status ps;
+          if (job == kJobMvX || job == kJobMvP) {
+            const float *v = job == kJobMvX ? hc->x : hc->p;
+            ps = gp_kmatvec(&kk, in.n, hc->X, thc, 1, v, 1, nullptr, hc->q, 1, pw, L.prod_bytes,
+                            stream);
+          } else {
+            HmcChain<float> *dc = (HmcChain<float> *)cp;
+            ps = gp_quadform_grad(&kk, in.n, hc->X, thc, 2, hc->Z, 2, hc->Z, 2, dc->ext_w,
+                                  dc->ext_res, dc->ext_res + in.nth, nullptr, 0, nullptr, 0, pw,
+                                  L.prod_bytes, stream);
+          }
+          if (ps != GP_OK) return ps;
+        } else {
+          e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);
+        }
         if (e == hipSuccess)
           e = f64 ? hmc_epilogue_f64(cp, prm, stream) : hmc_epilogue_f32(cp, prm, stream);
         if (e != hipSuccess) return hip_fail(e, "plain-mode step");

@@ -40,7 +40,8 @@ struct PassDesc {
   double *rec_fin;
   int nth;
   int nrec;
-  int use_mfma;  // 1: the matrix-core pair kernel (float, 8 <= R <= 32, d <= 16)
+  int use_mfma;  // 1: matrix-core pair kernel (float, 8 <= R <= 32, d <= 16); 2: cross-term
+                 //    kernel (GP_BF16X, d <= 64)
   void *mfma_scratch;  // scale exponents and partial maxima of the matrix-core pass
   int ib;              // matrix-core kernel: 16-row blocks per wave requested (1 or 2)
 };
@@ -69,6 +70,9 @@ size_t mfma_scratch_bytes();
 hipError_t launch_pass_f32(const PassDesc &p, hipStream_t s);
 hipError_t launch_pass_f64(const PassDesc &p, hipStream_t s);
 hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s);
+hipError_t launch_pass_xm(const PassDesc &p, hipStream_t s);
+int xm_rows_per_block(int has_grad_ard);
+size_t xm_scratch_bytes(int64_t n, int d);
 hipError_t launch_stage_f32(const void *X, int64_t n, int d, int dp, int kind,
                             const double *theta, char *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_stage_f64(const void *X, int64_t n, int d, int dp, int kind,

@@ -19,11 +19,13 @@ F64, F32, BF16X = 0, 1, 2
 NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
 CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED = 1, 2, 4, 8
+PHI_CG_MAXIT, PHI_NONFINITE = 1, 2
 
 EXPORTED = (
     "gp_last_error", "gp_status_string", "gp_n_theta", "gp_workspace_size", "gp_kmatvec",
     "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog", "gp_tune_workspace_size",
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
+    "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh",
 )
 
 
@@ -47,6 +49,11 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_inst", ctypes.c_int32), ("chains_per_inst", ctypes.c_int32),
                 ("n_points", ctypes.POINTER(ctypes.c_int64)), ("offsets", ctypes.POINTER(ctypes.c_int64)),
                 ("d", ctypes.POINTER(ctypes.c_int32)), ("x_offsets", ctypes.POINTER(ctypes.c_int64))]
+
+
+class PhiParams(ctypes.Structure):
+    _fields_ = [("n_poles", ctypes.c_int32), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("lambda_max", ctypes.c_double)]
 
 
 _LIB = None
@@ -98,6 +105,13 @@ def lib():
     L.gp_tune_entries.argtypes = []
     L.gp_tune_clear.restype = None
     L.gp_tune_clear.argtypes = []
+    L.gp_pole_weights.restype = _i32
+    L.gp_pole_weights.argtypes = [ctypes.c_double, ctypes.c_double, _i32, _vp, _vp]
+    L.gp_phi_workspace_size.restype = _sz
+    L.gp_phi_workspace_size.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams), _i64, _i32]
+    L.gp_phi_refresh.restype = _i32
+    L.gp_phi_refresh.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams), _i64, _vp, _vp,
+                                 _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
     _LIB = L
     return L
 
@@ -230,7 +244,7 @@ def hmc_workspace_size(kernel, params, batch):
 
 def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, d=None,
                  x_offsets=None, u=None, n_steps=20, dt=1e-2, cg_tol=1e-6, cg_maxit=1000,
-                 mode=BATCHED, ws=None, cg_iters=True):
+                 mode=BATCHED, ws=None, cg_iters=True, prec=None):
     """One HMC trajectory per chain through gp_hmc_leapfrog (packing as in include/gpk.h).
 
     theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, cg_iters).
@@ -245,7 +259,7 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
-    k = Kernel(kind_code(kind), prec_code(dt_), int(max(dims)), 0)
+    k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0)
     prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode))
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
     offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
@@ -301,3 +315,50 @@ def tune_entries():
 
 def tune_clear():
     lib().gp_tune_clear()
+
+
+def pole_weights(m, M, n_poles=15):
+    """(w, shifts) of the pole expansion of A^{-1/2} on [m, M], computed by the library (host)."""
+    import numpy as np
+    w = np.zeros(int(n_poles))
+    sh = np.zeros(int(n_poles))
+    _check(lib().gp_pole_weights(float(m), float(M), int(n_poles), w.ctypes.data_as(_vp),
+                                 sh.ctypes.data_as(_vp)))
+    return w, sh
+
+
+def phi_workspace_size(kernel, params, n, r):
+    return int(lib().gp_phi_workspace_size(ctypes.byref(kernel), ctypes.byref(params), int(n), int(r)))
+
+
+def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit=2000,
+                lambda_max=None, out=None, ws=None):
+    """phi = A(theta)^{-1/2} xi through gp_phi_refresh.  xi may be 1-D (one column).
+
+    Returns dict(phi, status, iters, bounds=(m, M))."""
+    squeeze = xi.dim() == 1
+    xi2 = xi[:, None] if squeeze else xi
+    _rowmajor(X, "X")
+    _rowmajor(xi2, "xi")
+    if X.stride(0) != X.shape[1]:
+        raise ValueError("X must be contiguous")
+    dev = X.device
+    _same(dev, X.dtype, xi=xi2)
+    _same(dev, torch.float64, theta=theta)
+    k = make_kernel(kind, X, prec)
+    prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0))
+    n, r = X.shape[0], xi2.shape[1]
+    if out is None:
+        out = torch.empty((n, r), dtype=X.dtype, device=dev)
+    out2 = out[:, None] if out.dim() == 1 else out
+    _rowmajor(out2, "out")
+    status = torch.empty(r, dtype=torch.int32, device=dev)
+    iters = torch.empty(r, dtype=torch.int32, device=dev)
+    bounds = (ctypes.c_double * 2)(0.0, 0.0)
+    w = _workspace(phi_workspace_size(k, prm, n, r), dev, ws)
+    _check(lib().gp_phi_refresh(ctypes.byref(k), ctypes.byref(prm), n, _p(X), _p(theta), r,
+                                _p(xi2), xi2.stride(0), _p(out2), out2.stride(0), _p(status),
+                                _p(iters), ctypes.cast(bounds, _vp), _p(w),
+                                0 if w is None else w.numel(), _stream(dev)))
+    return {"phi": out2[:, 0] if squeeze else out, "status": status, "iters": iters,
+            "bounds": (bounds[0], bounds[1])}

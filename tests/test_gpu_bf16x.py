@@ -1,0 +1,79 @@
+"""GP_BF16X products: the coordinate cross term on the matrix cores in bfloat16 hi/lo.
+
+Tolerance 3e-3 relative (the bfloat16 cross-term budget), on the whole product and on its
+off-diagonal part (K - alpha I) V: at d = 64 most kernel values vanish and A is close to
+(alpha + sigma^2) I, so the check on the full product alone would be met trivially.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gp as ogp
+from paper_2412_20884_amd import gpk, inputs as I
+from tests.gpu_util import col_rel_err, grad_rel_err, host, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 3e-3
+
+
+def _offdiag(out, V, th):
+    return out - (np.exp(th[0]) + np.exp(th[-1])) * V
+
+
+def _offdiag_err(out, ref, V, th):
+    """Column error of the off-diagonal part, relative to that part's norm but never to less
+    than 1e-2 of the whole column.  The squared distances come from the norm expansion
+    |a|^2 + |b|^2 - 2 a.b in float32, with an absolute error of a few eps32 |x~|^2 (x~ the
+    scaled coordinates, |x~|^2 ~ 60 at d = 64) even on the diagonal, i.e. ~1e-5 relative on every
+    kernel entry: an off-diagonal part far below the diagonal one is resolved only to that."""
+    num = np.linalg.norm(_offdiag(out, V, th) - _offdiag(ref, V, th), axis=0)
+    den = np.maximum(np.linalg.norm(_offdiag(ref, V, th), axis=0), 1e-2 * np.linalg.norm(ref, axis=0))
+    return float(np.max(num / den))
+
+
+@pytest.mark.parametrize("kind,d,lo,hi", [("iso", 3, None, None), ("ard", 8, 0.3, 3.0),
+                                          ("ard", 33, 0.5, 8.0), ("ard", 64, 0.5, 8.0)])
+@pytest.mark.parametrize("r", [1, 2, 16, 32])
+def test_kmatvec_bf16x(kind, d, lo, hi, r):
+    n = 3100
+    if kind == "iso":
+        p = I.iso_problem(n, d, 71, ell=0.15, r=r)
+    else:
+        p = I.ard_problem(n, d, 71 + d, lo=lo, hi=hi, r=r)
+    X, V = rounded(p["X"], torch.float32), rounded(p["V"], torch.float32)
+    th = p["theta"]
+    out = gpk.kmatvec(to_dev(X, torch.float32), to_dev(th, torch.float64), to_dev(V, torch.float32),
+                      kind, prec="bf16x")
+    torch.cuda.synchronize()
+    ref = ogp.matvec(X, th, kind, V)
+    o = host(out)
+    assert col_rel_err(o, ref) < TOL
+    assert _offdiag_err(o, ref, V, th) < TOL
+
+
+@pytest.mark.parametrize("kind,d", [("iso", 3), ("ard", 8), ("ard", 64)])
+@pytest.mark.parametrize("r", [2, 16])
+def test_quadform_bf16x(kind, d, r):
+    n = 2600
+    if kind == "iso":
+        p = I.iso_problem(n, d, 81, ell=0.15, r=r)
+    else:
+        p = I.ard_problem(n, d, 81 + d, lo=0.5, hi=8.0 if d == 64 else 3.0, r=r)
+    X, U = rounded(p["X"], torch.float32), rounded(p["U"], torch.float32)
+    th = p["theta"]
+    w = np.linspace(-0.5, 0.5, r) + (0.25 if r > 1 else 1.0)
+    Ud = to_dev(U, torch.float32)
+    res = gpk.quadform_grad(to_dev(X, torch.float32), to_dev(th, torch.float64), Ud, Ud,
+                            to_dev(w, torch.float64), kind, prec="bf16x", want_AU=True)
+    torch.cuda.synchronize()
+    ref = ogp.quadform_grad(X, th, kind, U, U, w)
+    scale = ogp.quadform_grad(X, th, kind, np.abs(U), np.abs(U), np.abs(w))["grad"]
+    au = host(res["AU"])
+    assert col_rel_err(au, ref["AU"]) < TOL
+    assert _offdiag_err(au, ref["AU"], U, th) < TOL
+    # at d = 64 the alpha component is dominated by the diagonal: compare it relative to its
+    # off-diagonal scale, floored as in _offdiag_err
+    K0 = np.exp(th[0])
+    offs = scale.copy()
+    offs[0] = scale[0] - K0 * np.sum(np.abs(w) * np.sum(U * U, axis=0))
+    assert grad_rel_err(host(res["grad"]), ref["grad"], np.maximum(offs, 1e-2 * scale)) < TOL

@@ -191,3 +191,28 @@ def test_graph_replays_match_batched_bitwise():
     for a, b in zip(outs[gpk.BATCHED], outs[gpk.GRAPH]):
         for x, z in zip(a, b):
             np.testing.assert_array_equal(x, z)
+
+
+def test_bf16x_plain_trajectory():
+    """GP_BF16X trajectories (plain mode, products on the cross-term kernel) against the FP64
+    oracle: the kernel values carry ~1e-4 relative error, so the 4-step trajectory agrees to
+    ~1e-5 in theta and ~1e-4 relative in the energies."""
+    p = I.ard_problem(1500, 20, 23, lo=0.5, hi=4.0, sigma2=0.05)
+    X, y, th = rounded(p["X"], torch.float32), rounded(p["y"], torch.float32), p["theta"]
+    phi = rounded(phi_exact(X, th, "ard", p["xi"]), torch.float32)
+    pi0 = np.random.default_rng(3).normal(size=22) * 0.5
+    Xd = to_dev(X, torch.float32)
+    thd, pid = to_dev(th, torch.float64), to_dev(pi0, torch.float64)
+    xd = torch.zeros(1500, dtype=torch.float32, device=DEV)
+    res = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float32), to_dev(phi, torch.float32), thd, pid, xd,
+                           "ard", [1500], [0], 1, n_steps=4, dt=0.02, cg_tol=1e-6, mode=gpk.PLAIN,
+                           prec="bf16x")
+    torch.cuda.synchronize()
+    th1, pi1 = ohmc.leapfrog(X, "ard", y, phi, th, pi0, 0.02, 4)
+    H1 = ohmc.hamiltonian(X, th1, "ard", y, phi, pi1)
+    assert res["status"].item() == 0
+    assert np.max(np.abs(host(thd) - th1)) < 1e-4
+    assert abs(res["H1"].item() - H1) < 1e-3 * abs(H1)
+    with pytest.raises(gpk.GpkError):
+        gpk.hmc_leapfrog(Xd, to_dev(y, torch.float32), to_dev(phi, torch.float32), thd, pid, xd,
+                         "ard", [1500], [0], 1, n_steps=1, mode=gpk.BATCHED, prec="bf16x")

@@ -1,0 +1,183 @@
+"""Gibbs refresh phi = A^{-1/2} xi (Section 3.1, eq. pex; Appendix A, eq. msqdisc) through
+gp_phi_refresh, against the oracle's pole expansion with exact (Cholesky) shifted solves.
+
+Tolerances.  Each shifted system stops at relative residual `tol`, which bounds the relative
+error of its solution by cond(A + lambda I) tol <= (M / m) tol; in float32 the attainable
+accuracy of the solves is of order (M / m) eps32 instead.  The oracle uses the same m and M (the
+m, M the library reports), so the expansion's own error cancels between the two.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gp as ogp, poles as opoles
+from paper_2412_20884_amd import gpk, inputs as I
+from tests.gpu_util import host, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+EPS32 = 2.0 ** -24
+
+
+def _problem(kind, n, d, seed, r, sigma2):
+    if kind == "iso":
+        p = I.iso_problem(n, d, seed, ell=0.2, sigma2=sigma2)
+    else:
+        p = I.ard_problem(n, d, seed, lo=0.3, hi=3.0, sigma2=sigma2)
+    xi = I.normal_matrix(n, r, seed, I.P_XI)
+    return p["X"], p["theta"], xi
+
+
+def _oracle(X, th, kind, xi, M, n_poles=15):
+    return opoles.inv_sqrt_apply(X, th, kind, xi, n_poles=n_poles, M=M)
+
+
+def _col_err(a, b):
+    return float(np.max(np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)))
+
+
+@pytest.mark.parametrize("kind,d", [("iso", 2), ("ard", 5)])
+@pytest.mark.parametrize("n", [1, 2, 300, 1500])
+@pytest.mark.parametrize("r", [1, 3])
+def test_phi_f64_vs_oracle(kind, d, n, r):
+    X, th, xi = _problem(kind, n, d, 90 + n + r, r, 1e-2)
+    M = opoles.gershgorin_upper(X, th, kind)
+    res = gpk.phi_refresh(to_dev(X, torch.float64), to_dev(th, torch.float64),
+                          to_dev(xi, torch.float64), kind, tol=1e-13, maxit=5000, lambda_max=M)
+    torch.cuda.synchronize()
+    m_used, M_used = res["bounds"]
+    assert m_used == pytest.approx(np.exp(th[-1]), rel=1e-15)
+    assert M_used == M
+    assert np.all(host(res["status"]) == 0)
+    ref = _oracle(X, th, kind, xi, M)
+    assert _col_err(host(res["phi"]), ref) < 1e-12 + 10 * (M / m_used) * 1e-13
+
+
+@pytest.mark.parametrize("kind,d", [("iso", 3), ("ard", 6)])
+def test_phi_f64_gershgorin_on_device(kind, d):
+    X, th, xi = _problem(kind, 1200, d, 7, 2, 1e-2)
+    res = gpk.phi_refresh(to_dev(X, torch.float64), to_dev(th, torch.float64),
+                          to_dev(xi, torch.float64), kind, tol=1e-13, maxit=5000)
+    torch.cuda.synchronize()
+    M_ref = opoles.gershgorin_upper(X, th, kind)
+    m_used, M_used = res["bounds"]
+    # the device bound is max_i (A 1)_i widened by 1e-12 relative
+    assert M_used == pytest.approx(M_ref * (1 + 1e-12), rel=1e-13)
+    ref = _oracle(X, th, kind, xi, M_used)
+    assert _col_err(host(res["phi"]), ref) < 1e-12 + 10 * (M_used / m_used) * 1e-13
+
+
+@pytest.mark.parametrize("kind,d,prec", [("iso", 3, None), ("ard", 8, None), ("ard", 20, "bf16x"),
+                                         ("iso", 3, "bf16x")])
+def test_phi_float32(kind, d, prec):
+    n, r = 2000, 2
+    X, th, xi = _problem(kind, n, d, 31 + d, r, 0.1)
+    Xr, xir = rounded(X, torch.float32), rounded(xi, torch.float32)
+    res = gpk.phi_refresh(to_dev(Xr, torch.float32), to_dev(th, torch.float64),
+                          to_dev(xir, torch.float32), kind, prec=prec, tol=1e-6, maxit=3000)
+    torch.cuda.synchronize()
+    m_used, M_used = res["bounds"]
+    assert np.all(host(res["status"]) == 0)
+    ref = _oracle(Xr, th, kind, xir, M_used)
+    err = _col_err(host(res["phi"]), ref)
+    # float32 solves: (M / m) eps32 per shifted system.  GP_BF16X forms the squared distances by
+    # the norm expansion, with an absolute error of a few eps32 max|x~|^2 (x~ the scaled,
+    # centred coordinates), i.e. a relative perturbation ln 2 of that on every kernel entry,
+    # amplified by the same condition number
+    ent = EPS32
+    if prec == "bf16x":
+        ell = np.exp(th[1:-1]) if kind == "ard" else np.exp(th[1])
+        xt = (Xr - Xr.mean(axis=0)) * np.sqrt(np.log2(np.e) / 2) / ell
+        ent = 8 * EPS32 * np.max(np.sum(xt * xt, axis=1)) * np.log(2) + EPS32
+    bound = 10 * (M_used / m_used) * ent
+    print(f"phi {kind} d={d} prec={prec}: rel err {err:.3e}, bound {bound:.3e}, "
+          f"M/m {M_used / m_used:.3e}, iters {host(res['iters'])}")
+    assert err < bound
+
+
+def test_phi_maxit_flag_and_iterations():
+    X, th, xi = _problem("iso", 800, 2, 3, 2, 1e-3)
+    Xd, thd, xid = to_dev(X, torch.float64), to_dev(th, torch.float64), to_dev(xi, torch.float64)
+    res = gpk.phi_refresh(Xd, thd, xid, "iso", tol=1e-13, maxit=3)
+    torch.cuda.synchronize()
+    assert np.all(host(res["status"]) == gpk.PHI_CG_MAXIT)
+    assert np.all(host(res["iters"]) == 3)
+    full = gpk.phi_refresh(Xd, thd, xid, "iso", tol=1e-10, maxit=5000)
+    torch.cuda.synchronize()
+    it = host(full["iters"])
+    assert np.all(host(full["status"]) == 0) and np.all(it > 3)
+    # the shifted systems converge no later than plain CG on A itself at the same tolerance
+    A = ogp.a_matrix(X, th, "iso")
+    for c in range(2):
+        x = np.zeros(800)
+        rv = xi[:, c].copy()
+        p = rv.copy()
+        rr = rv @ rv
+        k = 0
+        while np.sqrt(rr) > 1e-10 * np.linalg.norm(xi[:, c]) and k < 5000:
+            q = A @ p
+            a = rr / (p @ q)
+            x += a * p
+            rv -= a * q
+            rn = rv @ rv
+            p = rv + rn / rr * p
+            rr = rn
+            k += 1
+        assert it[c] <= k + 1
+
+
+def test_phi_zero_column_inplace_and_determinism():
+    X, th, xi = _problem("ard", 700, 4, 11, 3, 1e-2)
+    xi[:, 1] = 0.0
+    Xd, thd = to_dev(X, torch.float64), to_dev(th, torch.float64)
+    a = gpk.phi_refresh(Xd, thd, to_dev(xi, torch.float64), "ard", tol=1e-12, maxit=4000)
+    b = gpk.phi_refresh(Xd, thd, to_dev(xi, torch.float64), "ard", tol=1e-12, maxit=4000)
+    xin = to_dev(xi, torch.float64)
+    c = gpk.phi_refresh(Xd, thd, xin, "ard", tol=1e-12, maxit=4000, out=xin)
+    torch.cuda.synchronize()
+    pa = host(a["phi"])
+    assert np.array_equal(pa, host(b["phi"]))
+    assert np.array_equal(pa, host(c["phi"]))
+    assert np.all(pa[:, 1] == 0.0)
+    assert host(a["iters"])[1] == 0 and np.all(host(a["status"]) == 0)
+    ref = _oracle(X, th, "ard", xi, a["bounds"][1])
+    assert _col_err(pa[:, [0, 2]], ref[:, [0, 2]]) < 1e-7
+
+
+def test_phi_empty():
+    X = torch.zeros((0, 3), dtype=torch.float32, device="cuda:0")
+    th = to_dev(I.theta_iso(1.0, 0.2, 1e-2), torch.float64)
+    xi = torch.zeros((0, 2), dtype=torch.float32, device="cuda:0")
+    res = gpk.phi_refresh(X, th, xi, "iso")
+    torch.cuda.synchronize()
+    assert res["phi"].shape == (0, 2)
+    assert np.all(host(res["status"]) == 0) and np.all(host(res["iters"]) == 0)
+
+
+def test_phi_identities_at_ard8_size():
+    """At the ard8 workload's size (N = 65,536, d = 8) the oracle cannot run; check identities
+    that hold at any size.  With Phi = R(Xi), R = A^{-1/2}: Phi^T A Phi = Xi^T Xi (every column
+    pair), and with Psi = R(Phi) = A^{-1} Xi: psi_c^T A psi_c = xi_c^T psi_c.  (The residual
+    A Psi - Xi is not a usable check in float32 here: |A| |A^{-1} xi| reaches ~5e5 |xi|, so its
+    rounding floor alone is ~1e-2.)"""
+    w = I.ard8(r=2)
+    X = to_dev(rounded(w["X"], torch.float32), torch.float32)
+    th = to_dev(w["theta"], torch.float64)
+    xi = to_dev(I.normal_matrix(X.shape[0], 2, I.WORKLOAD_SEEDS["ard8"], I.P_XI), torch.float32)
+    r1 = gpk.phi_refresh(X, th, xi, "ard", tol=1e-6, maxit=5000)
+    r2 = gpk.phi_refresh(X, th, r1["phi"].contiguous(), "ard", tol=1e-6, maxit=5000)
+    Aphi = gpk.kmatvec(X, th, r1["phi"].contiguous(), "ard")
+    Apsi = gpk.kmatvec(X, th, r2["phi"].contiguous(), "ard")
+    torch.cuda.synchronize()
+    m_used, M_used = r1["bounds"]
+    phi, x, psi = host(r1["phi"]), host(xi), host(r2["phi"])
+    gram = phi.T @ host(Aphi)
+    gram_ref = x.T @ x
+    gerr = np.max(np.abs(gram - gram_ref)) / np.max(np.abs(np.diag(gram_ref)))
+    e_psi = np.sum(psi * host(Apsi), axis=0)
+    e_ref = np.sum(x * psi, axis=0)
+    perr = np.max(np.abs(e_psi - e_ref) / np.abs(e_ref))
+    print(f"ard8 phi: M/m {M_used / m_used:.3e}, iters {host(r1['iters'])} {host(r2['iters'])}, "
+          f"gram rel {gerr:.3e}, psi energy rel {perr:.3e}")
+    assert np.all(host(r1["status"]) == 0) and np.all(host(r2["status"]) == 0)
+    assert gerr < 1e-4
+    assert perr < 1e-3
