@@ -1,6 +1,6 @@
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-cpu] [--no-ard64]
 
 A step is one fused gp_quadform_grad pass over the large3 workload (N = 2^20 points uniform in
 [0,1]^3, isotropic SE kernel l = 0.05, alpha = 1, sigma^2 = 1e-3, 32 N(0,1) auxiliary vectors Z):
@@ -8,8 +8,10 @@ A Z, q_c = z_c^T A z_c and grad_theta sum_c q_c in one pass over all N^2 pairs. 
 resident in HBM before the timed region.  The value is pair evaluations per second (N^2 per
 step).  The JSON line also carries the roofline of the dominant kernel (the matrix-core pair
 kernel), the FP64 oracle timed on a bounded row slab of the same workload on the host cores,
-a sampled parity check of the timed outputs, and the batched-vs-plain HMC leapfrog comparison
-on the batched workload (64 instances, 8 chains each, 20-step trajectories).
+a sampled parity check of the timed outputs, the batched-vs-plain HMC leapfrog comparison on the
+batched workload (64 instances, 8 chains each, 20-step trajectories) with phi drawn by the
+device Gibbs refresh (timed as its own leg), and the d = 64 workload in the bfloat16
+cross-term precision (product and force-pass rates, one short trajectory).
 """
 from __future__ import annotations
 
@@ -34,7 +36,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def bench_large3(steps, warmup, tune=True):
+def bench_large3(steps, warmup, tune=True, tune_load=None):
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
@@ -43,7 +45,11 @@ def bench_large3(steps, warmup, tune=True):
     w = inputs.large3()
     n, r = w["X"].shape[0], w["Z"].shape[1]
     tuned = None
-    if tune:
+    if tune_load:
+        gpk.tune_load(tune_load)
+        tuned = {"table": tune_load, "loaded": True}
+        log(f"tuning table loaded from {tune_load}")
+    elif tune:
         t0 = time.perf_counter()
         gpk.tune("iso", 3, n, r, torch.float32, with_grad=True)
         path = os.path.join(ROOT, "gpurun_out", "tune_large3.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
@@ -144,10 +150,29 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
     xoffs = np.cumsum([0] + [a * b for a, b in zip(ns, ds)][:-1])
     X = torch.tensor(np.concatenate([b["X"].ravel() for b in inst]), dtype=torch.float32, device=dev)[:, None]
     y = torch.tensor(np.concatenate([b["y"] for b in inst]), dtype=torch.float32, device=dev)
-    # phi = xi / sqrt(alpha + sigma^2): the cost does not depend on phi's law
-    s2 = float(np.exp(inst[0]["theta"][-1]))
-    phi = torch.tensor(np.concatenate([(b["xi"] / np.sqrt(1.0 + s2)).ravel() for b in inst]),
-                       dtype=torch.float32, device=dev)
+    # phi | theta_0 for every chain by the Gibbs refresh (pole expansion, multi-shift CG), one
+    # call per instance with its 8 chains' xi as the right-hand sides; timed as its own leg
+    phi = torch.empty(sum(ns) * C, dtype=torch.float32, device=dev)
+    t_phi, it_phi, cols = 0.0, [], 0
+    for bi, b in enumerate(inst):
+        Xb = X[xoffs[bi]:xoffs[bi] + ns[bi] * ds[bi]].view(ns[bi], ds[bi])
+        xi = torch.tensor(b["xi"].T.copy(), dtype=torch.float32, device=dev)
+        thb = torch.tensor(b["theta"], dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gpk.phi_refresh(Xb, thb, xi, "ard", tol=1e-6, maxit=3000)
+        torch.cuda.synchronize()
+        t_phi += time.perf_counter() - t0
+        if np.any(r["status"].cpu().numpy() != 0):
+            raise RuntimeError(f"phi refresh did not converge on instance {bi}")
+        it_phi.append(int(r["iters"].max()))
+        cols += C
+        phi[C * offs[bi]:C * (offs[bi] + ns[bi])] = r["phi"].t().contiguous().view(-1)
+    refresh = {"chains_refreshed_per_s": cols / t_phi, "seconds": t_phi,
+               "multishift_cg_iterations": it_phi, "n_poles": 15, "tol": 1e-6,
+               "workload": "phi = A(theta_0)^{-1/2} xi for the 8 chains of each instance of the subset "
+                           "below (one call per instance, 8 right-hand sides), FP32"}
+    log(f"phi refresh: {refresh}")
     th0 = np.concatenate([np.tile(b["theta"], C) for b in inst])
     pi0 = np.concatenate([b["pi"].ravel() for b in inst])
     u = torch.tensor(np.concatenate([b["u"] for b in inst]), dtype=torch.float64, device=dev)
@@ -207,9 +232,65 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
         torch.cuda.empty_cache()
     if "graph" in out and "plain" in out:
         out["speedup_batched_vs_plain"] = out["graph"]["chain_steps_per_s"] / out["plain"]["chain_steps_per_s"]
+    out["phi_refresh"] = refresh
     out["workload"] = (f"batched: instances 0,{subset},{2 * subset},.. ({len(inst)} of 64; N_b in [2048, 32768], "
-                       f"d_b in {{4,8,16}}), ARD SE, sigma^2=0.1, 8 chains each, 20 leapfrog steps, "
-                       f"dt 1e-2, CG tol 1e-6, FP32; N_b = {ns}, d_b = {ds}")
+                       f"d_b in {{4,8,16}}), ARD SE, sigma^2=0.1, 8 chains each, {wl['n_steps']} leapfrog "
+                       f"steps, dt {wl['dt']:g}, CG tol 1e-6, FP32, phi from the device Gibbs refresh; "
+                       f"N_b = {ns}, d_b = {ds}")
+    return out
+
+
+def bench_ard64(n_chain_steps=4):
+    """The d = 64 workload with GP_BF16X (bfloat16 cross term, compensated norms): rates of the
+    product (R = 1, one CG iteration) and of the fused force pass (R = 2, [x | phi] with
+    w = (-1/2, 1/2)), and one short plain-mode trajectory of one chain."""
+    import torch
+
+    from paper_2412_20884_amd import gpk, inputs
+
+    dev = "cuda:0"
+    wl = inputs.ard64()
+    n = wl["X"].shape[0]
+    X = torch.tensor(wl["X"], dtype=torch.float32, device=dev)
+    th = torch.tensor(wl["theta"], dtype=torch.float64, device=dev)
+    y = torch.tensor(wl["y"], dtype=torch.float32, device=dev)
+    V = torch.tensor(wl["xi"][:2].T.copy(), dtype=torch.float32, device=dev)
+    w = torch.tensor([-0.5, 0.5], dtype=torch.float64, device=dev)
+    out = {"workload": "ard64: N=262,144 points N(0, I_64), ARD SE (66 hyperparameters, l_k "
+                       "log-uniform [0.5, 8]), sigma^2=1e-2, GP_BF16X", "N": n, "d": 64}
+    ws = torch.empty(gpk.workspace_size(gpk.make_kernel("ard", X, "bf16x"), n, 2), dtype=torch.uint8, device=dev)
+    for name, fn in (("kmatvec_r1", lambda: gpk.kmatvec(X, th, V[:, :1].contiguous(), "ard", prec="bf16x", ws=ws)),
+                     ("force_pass_r2", lambda: gpk.quadform_grad(X, th, V, V, w, "ard", prec="bf16x", ws=ws))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        out[name] = {"seconds": t, "pair_evals_per_s": n * n / t}
+        log(f"ard64 {name}: {out[name]}")
+    # one chain, a short trajectory (plain mode: GP_BF16X runs through the product kernels)
+    phi = gpk.phi_refresh(X, th, torch.tensor(wl["xi"][0], dtype=torch.float32, device=dev), "ard",
+                          prec="bf16x", tol=1e-6, maxit=500)
+    torch.cuda.synchronize()
+    out["phi_refresh_iterations"] = int(phi["iters"][0])
+    thc = th.clone()
+    pi = torch.tensor(wl["pi"][0], dtype=torch.float64, device=dev)
+    x = torch.zeros(n, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi["phi"].contiguous(), thc, pi, x, "ard", [n], [0], 1,
+                         d=[64], n_steps=n_chain_steps, dt=wl["dt"], cg_tol=1e-6, cg_maxit=500,
+                         mode=gpk.PLAIN, prec="bf16x")
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["trajectory"] = {"chain_steps": n_chain_steps, "seconds": t,
+                         "chain_steps_per_s": n_chain_steps / t,
+                         "cg_iterations": int(r["cg_iters"][0]), "status": int(r["status"][0]),
+                         "H0": float(r["H0"][0]), "H1": float(r["H1"][0])}
+    log(f"ard64 trajectory: {out['trajectory']}")
     return out
 
 
@@ -236,9 +317,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--leapfrog-modes", default="graph,plain")
-    ap.add_argument("--leapfrog-subset", type=int, default=8)
+    ap.add_argument("--leapfrog-subset", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-ard64", action="store_true")
+    ap.add_argument("--tune-load", default=None, help="load a saved tuning table instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
@@ -253,7 +336,7 @@ def main():
     if args.copy_calibration:
         log(f"copy calibration: {copy_calibration()}")
     log("large3: generating inputs and warming up")
-    b = bench_large3(args.steps, args.warmup, tune=not args.no_tune)
+    b = bench_large3(args.steps, args.warmup, tune=not args.no_tune, tune_load=args.tune_load)
     n = b["n"]
     t_step = float(np.median(b["per_call"]))
     value = n * n * args.steps / b["wall"]
@@ -283,6 +366,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     if not args.no_leapfrog:
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset)
+    if not args.no_ard64:
+        line["ard64_bf16x"] = bench_ard64()
     print(json.dumps(line), flush=True)
 
 

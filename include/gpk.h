@@ -13,6 +13,11 @@
  *   theta = (log alpha, log l_1 .. log l_L, log sigma^2), natural logs, L = 1 (ISO) or d (ARD),
  *   n_theta = L + 2.  In this library "K_theta" always means the full A(theta) unless
  *   GP_NO_NOISE is set.
+ *   GP_SE_CHEB, the non-stationary amplitude kernel of Section 4:
+ *     K_ij = exp(C(x_i)) exp(C(x_j)) exp(-|x_i - x_j|^2 / (2 l^2)),
+ *     C(x) = sum_{m_1..m_d < N_cheb} Theta_{m_1..m_d} T_{m_1}(x^1) ... T_{m_d}(x^d),
+ *   T_m the Chebyshev polynomials of the first kind (points are meant to lie in [-1, 1]^d);
+ *   theta = (Theta flattened with m_1 slowest, log l, log sigma^2), n_theta = N_cheb^d + 2.
  *
  * Conventions common to every entry point
  *   - Ownership: every array argument is caller-owned memory; the library never allocates,
@@ -58,16 +63,17 @@ enum {
   GP_ERR_HIP = 5          /* a HIP launch or runtime call failed */
 };
 
-enum { GP_SE_ISO = 0, GP_SE_ARD = 1 };
+enum { GP_SE_ISO = 0, GP_SE_ARD = 1, GP_SE_CHEB = 2 };
 enum { GP_F64 = 0, GP_F32 = 1, GP_BF16X = 2 };
 enum { GP_NO_NOISE = 1 /* apply K(theta) (eq. kernmat) instead of A(theta) */ };
 
 /* Kernel description.  d: 1..64 coordinates. */
 typedef struct {
-  int32_t kind;  /* GP_SE_ISO or GP_SE_ARD */
-  int32_t prec;  /* GP_F64, GP_F32 or GP_BF16X */
-  int32_t d;     /* spatial dimension */
-  int32_t flags; /* 0 or GP_NO_NOISE */
+  int32_t kind;   /* GP_SE_ISO, GP_SE_ARD or GP_SE_CHEB */
+  int32_t prec;   /* GP_F64, GP_F32 or GP_BF16X */
+  int32_t d;      /* spatial dimension */
+  int32_t flags;  /* 0 or GP_NO_NOISE */
+  int32_t n_cheb; /* GP_SE_CHEB: Chebyshev order N_cheb >= 1 with N_cheb^d <= 64; else ignored */
 } gp_kernel;
 
 /* Per-chain status bits written by gp_hmc_leapfrog; any set bit forces a reject. */
@@ -120,7 +126,12 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
  *   dQ/dlog alpha   = sum_ij K_ij S_ij,        S_ij = sum_c w_c u_ic v_jc
  *   dQ/dlog l_k     = sum_ij K_ij (x_ik - x_jk)^2 / l_k^2 S_ij   (ISO: r_ij^2 / l^2)
  *   dQ/dlog sigma^2 = sigma^2 sum_c w_c u_c . v_c
- * Kernel entries are recomputed, never stored.  GP_NO_NOISE is not accepted here.
+ * and for GP_SE_CHEB (Section 4), with phi_m(x) = prod_k T_{m_k}(x^k),
+ *   dQ/dTheta_m     = sum_ij K_ij (phi_m(x_i) + phi_m(x_j)) S_ij
+ *                   = sum_i phi_m(x_i) e^{C(x_i)} sum_c w_c [u_ic (K~ D v_c)_i + v_ic (K~ D u_c)_i]
+ * (K~ the unit-amplitude SE kernel, D = diag(e^{C(x_i)})), computed from the products of the
+ * same pass.  Kernel entries are recomputed, never stored.  With GP_NO_NOISE the form is in
+ * K(theta) (eq. kernmat) and the sigma^2 component of the gradient is 0.
  *
  *   U, V       device, n x r (r in 1..32), leading dimensions ldu, ldv >= r; U may equal V
  *   w          device double[r] weights, or NULL (all 1)

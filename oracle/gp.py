@@ -17,6 +17,16 @@ Definitions followed (paper section / equation):
         dQ/dlog sigma^2  = sigma^2 sum_c w_c u_c . v_c
     with S_ij = sum_c w_c u_ic v_jc.
 
+  * Chebyshev-amplitude kernel, Section 4 (the paper's experiments):
+        K(x,x') = exp(C(x)) exp(C(x')) exp(-|x-x'|^2 / (2 l^2)),
+        C(x) = sum_{m_1..m_d = 0}^{N_cheb - 1} Theta_{m_1..m_d} T_{m_1}(x^1) ... T_{m_d}(x^d),
+    T_m the Chebyshev polynomials of the first kind, points in the reference box [-1,1]^d.
+    theta = (Theta flattened with m_1 slowest, log l, log sigma^2): N_cheb^d + 2 entries.
+    Derivatives (same Q, S as above):
+        dQ/dTheta_m     = sum_ij K_ij (phi_m(x_i) + phi_m(x_j)) S_ij,  phi_m = prod_k T_{m_k}(x^k)
+        dQ/dlog l       = sum_ij K_ij r_ij^2 / l^2 S_ij
+        dQ/dlog sigma^2 = sigma^2 sum_c w_c u_c . v_c
+
 Everything is computed with direct coordinate differences in float64, densely, one block of
 rows at a time (a block of rows of A is formed explicitly; only the row partition is a choice
 made here, the arithmetic of each entry is the definition).
@@ -30,22 +40,42 @@ import numpy as np
 
 ISO = "iso"
 ARD = "ard"
+CHEB = "cheb"
 
 
-def n_theta(kind: str, d: int) -> int:
-    """Number of hyperparameters: (log alpha, log l..., log sigma^2)."""
+def cheb_order(n_theta_total: int, d: int) -> int:
+    """N_cheb from the length of a Chebyshev-kernel theta (N_cheb^d + 2 entries)."""
+    m = n_theta_total - 2
+    n = max(1, int(round(m ** (1.0 / d))))
+    for c in (n - 1, n, n + 1):
+        if c >= 1 and c ** d == m:
+            return c
+    raise ValueError(f"theta of length {n_theta_total} is not N_cheb^{d} + 2")
+
+
+def n_theta(kind: str, d: int, n_cheb: int | None = None) -> int:
+    """Number of hyperparameters: (log alpha, log l..., log sigma^2), or for the Chebyshev
+    kernel (Theta (N_cheb^d), log l, log sigma^2)."""
     if kind == ISO:
         return 3
     if kind == ARD:
         return d + 2
+    if kind == CHEB:
+        if n_cheb is None:
+            raise ValueError("the Chebyshev kernel needs n_cheb")
+        return n_cheb ** d + 2
     raise ValueError(f"unknown kernel kind {kind!r}")
 
 
 def unpack_theta(theta, kind: str, d: int):
-    """theta -> (alpha, length-scales per coordinate (array of d), sigma^2)."""
+    """theta -> (alpha, length-scales per coordinate (array of d), sigma^2).
+    For the Chebyshev kernel alpha is 1 (the amplitude is exp(C(x)) exp(C(x')))."""
     theta = np.asarray(theta, dtype=np.float64)
-    if theta.shape != (n_theta(kind, d),):
-        raise ValueError(f"theta has shape {theta.shape}, expected ({n_theta(kind, d)},)")
+    nt = n_theta(kind, d, cheb_order(theta.shape[0], d) if kind == CHEB else None)
+    if theta.shape != (nt,):
+        raise ValueError(f"theta has shape {theta.shape}, expected ({nt},)")
+    if kind == CHEB:
+        return 1.0, np.full(d, np.exp(theta[-2])), np.exp(theta[-1])
     alpha = np.exp(theta[0])
     if kind == ISO:
         ell = np.full(d, np.exp(theta[1]))
@@ -53,6 +83,25 @@ def unpack_theta(theta, kind: str, d: int):
         ell = np.exp(theta[1:1 + d])
     sigma2 = np.exp(theta[-1])
     return alpha, ell, sigma2
+
+
+def cheb_basis(X, n_cheb: int):
+    """phi_m(x_i) = prod_k T_{m_k}(x_i^k) for every multi-index m (m_1 slowest): N x N_cheb^d."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    out = np.ones((n, 1))
+    for k in range(d):
+        Tk = np.polynomial.chebyshev.chebvander(X[:, k], n_cheb - 1)   # T_0..T_{N_cheb-1}
+        out = (out[:, :, None] * Tk[:, None, :]).reshape(n, -1)
+    return out
+
+
+def cheb_log_amplitude(X, theta):
+    """C(x_i) = sum_m Theta_m phi_m(x_i) (Section 4)."""
+    X = np.asarray(X, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    nc = cheb_order(theta.shape[0], X.shape[1])
+    return cheb_basis(X, nc) @ theta[:-2]
 
 
 def _scaled_sq_diff(Xa, Xb, ell, k):
@@ -70,6 +119,10 @@ def kernel_block(Xa, Xb, theta, kind: str):
     e = np.zeros((Xa.shape[0], Xb.shape[0]))
     for k in range(d):
         e += _scaled_sq_diff(Xa, Xb, ell, k)
+    if kind == CHEB:
+        amp_a = np.exp(cheb_log_amplitude(Xa, theta))
+        amp_b = np.exp(cheb_log_amplitude(Xb, theta))
+        return amp_a[:, None] * amp_b[None, :] * np.exp(-0.5 * e)
     return alpha * np.exp(-0.5 * e)
 
 
@@ -146,7 +199,10 @@ def quadform_grad(X, theta, kind: str, U, V, w=None, rows=None, workers: int | N
         raise ValueError("U and V must both be N x R")
     w = np.ones(R) if w is None else np.asarray(w, dtype=np.float64)
     alpha, ell, sigma2 = unpack_theta(theta, kind, d)
-    nt = n_theta(kind, d)
+    nt = len(theta)
+    if kind == CHEB:
+        Phi = cheb_basis(X, cheb_order(nt, d))
+        amp = np.exp(Phi @ np.asarray(theta, dtype=np.float64)[:-2])
     rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
     blocks = _row_blocks(rows, n)
     offs = np.cumsum([0] + [len(b) for b in blocks])[:-1]
@@ -163,7 +219,10 @@ def quadform_grad(X, theta, kind: str, U, V, w=None, rows=None, workers: int | N
         e = np.zeros((len(blk), n))
         for k in range(d):
             e += _scaled_sq_diff(Xb, X, ell, k)
-        K = alpha * np.exp(-0.5 * e)
+        if kind == CHEB:
+            K = amp[blk][:, None] * amp[None, :] * np.exp(-0.5 * e)
+        else:
+            K = alpha * np.exp(-0.5 * e)
         av = K @ V + sigma2 * V[blk]
         au = K @ U + sigma2 * U[blk]
         AV[lo:lo + len(blk)] = av
@@ -171,10 +230,15 @@ def quadform_grad(X, theta, kind: str, U, V, w=None, rows=None, workers: int | N
         S = (U[blk] * w[None, :]) @ V.T          # S_ij = sum_c w_c u_ic v_jc
         W = K * S
         g = np.zeros(nt)
-        g[0] = W.sum()                            # dK/dlog alpha = K
-        if kind == ISO:
+        if kind == CHEB:
+            # dK_ij/dTheta_m = (phi_m(x_i) + phi_m(x_j)) K_ij, summed against S_ij
+            g[:-2] = Phi[blk].T @ W.sum(axis=1) + Phi.T @ W.sum(axis=0)
+            g[-2] = (W * e).sum()                 # dK/dlog l = K r^2 / l^2
+        elif kind == ISO:
+            g[0] = W.sum()                        # dK/dlog alpha = K
             g[1] = (W * e).sum()                  # dK/dlog l = K r^2 / l^2
         else:
+            g[0] = W.sum()
             for k in range(d):
                 g[1 + k] = (W * _scaled_sq_diff(Xb, X, ell, k)).sum()
         g[-1] = sigma2 * np.sum(w[None, :] * U[blk] * V[blk])   # dA/dlog sigma^2 = sigma^2 I

@@ -23,17 +23,18 @@ def _chunks(r):
 
 class KMatVec(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X, theta, V, kind="iso"):
+    def forward(ctx, X, theta, V, kind="iso", n_cheb=0):
         ctx.kind = kind
+        ctx.n_cheb = n_cheb
         ctx.save_for_backward(X, theta, V)
-        return gpk.kmatvec(X, theta, V.contiguous(), kind)
+        return gpk.kmatvec(X, theta, V.contiguous(), kind, n_cheb=n_cheb)
 
     @staticmethod
     def backward(ctx, G):
         X, theta, V = ctx.saved_tensors
         need_t, need_v = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         if not (need_t or need_v):
-            return None, None, None, None
+            return None, None, None, None, None
         G = G.contiguous()
         V = V.contiguous()
         squeeze = V.dim() == 1
@@ -43,25 +44,28 @@ class KMatVec(torch.autograd.Function):
         dV = torch.empty_like(V2) if need_v else None
         for c0, c1 in _chunks(V2.shape[1]):
             res = gpk.quadform_grad(X, theta, G2[:, c0:c1].contiguous(), V2[:, c0:c1].contiguous(), None,
-                                    ctx.kind, want_grad=need_t, want_quad=False, want_AU=need_v)
+                                    ctx.kind, want_grad=need_t, want_quad=False, want_AU=need_v,
+                                    n_cheb=ctx.n_cheb)
             if need_t:
                 dtheta += res["grad"]
             if need_v:
                 dV[:, c0:c1] = res["AU"]
         if need_v and squeeze:
             dV = dV[:, 0]
-        return None, dtheta, dV, None
+        return None, dtheta, dV, None, None
 
 
 class QuadForm(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X, theta, U, V, kind="iso"):
+    def forward(ctx, X, theta, U, V, kind="iso", n_cheb=0):
         if U.shape[1] > _MAX_R:
             raise ValueError("QuadForm takes at most 32 columns")
         U = U.contiguous()
         V = V.contiguous()
-        res = gpk.quadform_grad(X, theta, U, V, None, kind, want_grad=False, want_quad=True, want_AV=True)
+        res = gpk.quadform_grad(X, theta, U, V, None, kind, want_grad=False, want_quad=True, want_AV=True,
+                                n_cheb=n_cheb)
         ctx.kind = kind
+        ctx.n_cheb = n_cheb
         ctx.save_for_backward(X, theta, U, V, res["AV"])
         return res["quad"]
 
@@ -70,19 +74,19 @@ class QuadForm(torch.autograd.Function):
         X, theta, U, V, AV = ctx.saved_tensors
         need_t, need_u, need_v = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[3]
         if not (need_t or need_u or need_v):
-            return None, None, None, None, None
+            return None, None, None, None, None, None
         g = g.contiguous().to(torch.float64)
         res = gpk.quadform_grad(X, theta, U, V, g, ctx.kind, want_grad=need_t, want_quad=not need_t,
-                                want_AU=need_v)
+                                want_AU=need_v, n_cheb=ctx.n_cheb)
         gd = g.to(U.dtype)[None, :]
         dU = AV * gd if need_u else None
         dV = res["AU"] * gd if need_v else None
-        return None, res["grad"] if need_t else None, dU, dV, None
+        return None, res["grad"] if need_t else None, dU, dV, None, None
 
 
-def kmatvec(X, theta, V, kind="iso"):
-    return KMatVec.apply(X, theta, V, kind)
+def kmatvec(X, theta, V, kind="iso", n_cheb=0):
+    return KMatVec.apply(X, theta, V, kind, n_cheb)
 
 
-def quadform(X, theta, U, V=None, kind="iso"):
-    return QuadForm.apply(X, theta, U, U if V is None else V, kind)
+def quadform(X, theta, U, V=None, kind="iso", n_cheb=0):
+    return QuadForm.apply(X, theta, U, U if V is None else V, kind, n_cheb)

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "cheb.h"
 #include "gpk.h"
 #include "pass.h"
 #include "tune.h"
@@ -88,18 +89,24 @@ hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStrea
 
 static gp_status check_kernel(const gp_kernel *k, bool allow_no_noise) {
   if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
-  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD)
-    return fail(GP_ERR_ARG, "kernel kind %d is not GP_SE_ISO or GP_SE_ARD", k->kind);
+  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD && k->kind != GP_SE_CHEB)
+    return fail(GP_ERR_ARG, "kernel kind %d is not GP_SE_ISO, GP_SE_ARD or GP_SE_CHEB", k->kind);
   if (k->prec != GP_F64 && k->prec != GP_F32 && k->prec != GP_BF16X)
     return fail(GP_ERR_ARG, "precision %d is not GP_F64, GP_F32 or GP_BF16X", k->prec);
   if (k->d < 1 || k->d > kMaxD) return fail(GP_ERR_SHAPE, "d = %d outside 1..%d", k->d, kMaxD);
   if (k->flags & ~GP_NO_NOISE) return fail(GP_ERR_ARG, "unknown flag bits 0x%x", k->flags);
   if (!allow_no_noise && (k->flags & GP_NO_NOISE))
     return fail(GP_ERR_ARG, "GP_NO_NOISE is not accepted by this entry point");
+  if (k->kind == GP_SE_CHEB && cheb_terms(k) < 0)
+    return fail(GP_ERR_ARG, "GP_SE_CHEB needs n_cheb >= 1 with n_cheb^d <= 64 (n_cheb = %d, d = %d)",
+                k->n_cheb, k->d);
   return GP_OK;
 }
 
-static int nth_of(const gp_kernel *k) { return k->kind == GP_SE_ISO ? 3 : k->d + 2; }
+static int nth_of(const gp_kernel *k) {
+  if (k->kind == GP_SE_CHEB) return cheb_terms(k) + 2;
+  return k->kind == GP_SE_ISO ? 3 : k->d + 2;
+}
 
 static size_t elem_size(int prec) { return prec == GP_F64 ? sizeof(double) : sizeof(float); }
 
@@ -189,6 +196,7 @@ static PassDesc base_desc(const gp_kernel *k, const Plan &pl, int64_t n, const d
   p.use_mfma = pl.use_mfma;
   p.mfma_scratch = ws + pl.L.scratch;
   p.ib = pl.ib;
+  p.no_noise = (k->flags & GP_NO_NOISE) ? 1 : 0;
   return p;
 }
 
@@ -241,6 +249,7 @@ int32_t gp_n_theta(const gp_kernel *k) {
 size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
   if (check_kernel(k, true) != GP_OK || n < 0 || r < 0) return 0;
   if (n == 0 || r == 0) return 0;
+  if (k->kind == GP_SE_CHEB) return cheb_workspace_size(k, n, r);
   return make_plan(k, n, r, -1).L.total;
 }
 
@@ -259,6 +268,8 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
                 (long long)ldv, (long long)ldo, r);
   const size_t es = elem_size(k->prec);
   if (overlap(V, n, ldv, r, out, n, ldo, r, es)) return fail(GP_ERR_ARG, "out overlaps V");
+  if (k->kind == GP_SE_CHEB)
+    return cheb_kmatvec(k, n, X, theta, r, V, ldv, col_shift, out, ldo, ws, ws_bytes, stream);
   const Plan pl = make_plan(k, n, r, 0);
   if (!ws || ws_bytes < pl.L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
@@ -293,7 +304,7 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
                            int64_t ldau, void *AV, int64_t ldav, void *ws, size_t ws_bytes,
                            hipStream_t stream) {
   clear_error();
-  gp_status st = check_kernel(k, false);
+  gp_status st = check_kernel(k, true);
   if (st) return st;
   if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
   if (r < 1 || r > kMaxRPass) return fail(GP_ERR_SHAPE, "r = %d outside 1..%d", r, kMaxRPass);
@@ -315,6 +326,9 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
       overlap(AV, n, ldav, r, U, n, ldu, r, es) || overlap(AV, n, ldav, r, V, n, ldv, r, es) ||
       overlap(AU, n, ldau, r, AV, n, ldav, r, es))
     return fail(GP_ERR_ARG, "an output overlaps an input or the other output");
+  if (k->kind == GP_SE_CHEB)
+    return cheb_quadform_grad(k, n, X, theta, r, U, ldu, V, ldv, w, grad_theta, quad, AU, ldau,
+                              AV, ldav, ws, ws_bytes, stream);
   const Plan pl = make_plan(k, n, r, 1);
   if (!ws || ws_bytes < pl.L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,

@@ -48,6 +48,10 @@ struct ChainLayout {
 
 size_t chain_bytes(int prec) { return prec == GP_F64 ? sizeof(HmcChain<double>) : sizeof(HmcChain<float>); }
 
+// Chains whose jobs run through the product entry points (gp_kmatvec / gp_quadform_grad) rather
+// than the persistent tile kernels: the bfloat16 cross term and the Chebyshev-amplitude kernel.
+bool uses_ext(int prec, int kind) { return prec == GP_BF16X || kind == GP_SE_CHEB; }
+
 int plain_splits(int64_t n) {
   const int64_t rb = (n + kHmcTile - 1) / kHmcTile;
   int64_t s = (1024 + rb - 1) / rb;
@@ -70,7 +74,7 @@ size_t region_bytes(const InstInfo &in, int prec, int n_cs) {
 }
 
 ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode,
-                        int kind) {
+                        int kind, int n_cheb) {
   ChainLayout L;
   const int nc = (int)inst.size() * chains;
   size_t o = 0;
@@ -85,7 +89,7 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
   L.chains = o;
   o = align256(o + chain_bytes(prec) * (size_t)nc);
   for (const InstInfo &in : inst) {
-    const int n_cs = (mode == GP_HMC_PLAIN && prec != GP_BF16X) ? plain_splits(in.n) : 1;
+    const int n_cs = (mode == GP_HMC_PLAIN && !uses_ext(prec, kind)) ? plain_splits(in.n) : 1;
     const int n_rb = (int)((in.n + kHmcTile - 1) / kHmcTile);
     for (int h = 0; h < chains; ++h) {
       L.per_chain.push_back(o);
@@ -96,14 +100,15 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
   }
   L.prod = o;
   L.prod_bytes = 0;
-  if (prec == GP_BF16X) {
+  if (uses_ext(prec, kind)) {
     // one product workspace, reused by every (sequentially processed) chain
     for (const InstInfo &in : inst) {
       gp_kernel kk;
       kk.kind = kind;
-      kk.prec = GP_BF16X;
+      kk.prec = prec;
       kk.d = in.d;
       kk.flags = 0;
+      kk.n_cheb = n_cheb;
       const size_t b = gp_workspace_size(&kk, in.n, 2);
       if (b > L.prod_bytes) L.prod_bytes = b;
     }
@@ -116,7 +121,8 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
 gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
                   std::vector<InstInfo> &inst) {
   if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
-  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD) return fail(GP_ERR_ARG, "bad kernel kind");
+  if (k->kind != GP_SE_ISO && k->kind != GP_SE_ARD && k->kind != GP_SE_CHEB)
+    return fail(GP_ERR_ARG, "bad kernel kind");
   if (k->prec != GP_F64 && k->prec != GP_F32 && k->prec != GP_BF16X)
     return fail(GP_ERR_ARG, "precision %d is not GP_F64, GP_F32 or GP_BF16X", k->prec);
   if (k->flags != 0) return fail(GP_ERR_ARG, "kernel flags must be 0 for gp_hmc_leapfrog");
@@ -126,8 +132,8 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   if (p->cg_maxit < 1) return fail(GP_ERR_ARG, "cg_maxit must be >= 1");
   if (p->mode != GP_HMC_PLAIN && p->mode != GP_HMC_BATCHED && p->mode != GP_HMC_GRAPH)
     return fail(GP_ERR_ARG, "unknown mode %d", p->mode);
-  if (k->prec == GP_BF16X && p->mode != GP_HMC_PLAIN)
-    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories run in GP_HMC_PLAIN mode");
+  if (uses_ext(k->prec, k->kind) && p->mode != GP_HMC_PLAIN)
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X and GP_SE_CHEB trajectories run in GP_HMC_PLAIN mode");
   if (!b) return fail(GP_ERR_ARG, "batch is NULL");
   if (b->n_inst < 1 || b->chains_per_inst < 1)
     return fail(GP_ERR_SHAPE, "n_inst and chains_per_inst must be >= 1");
@@ -143,7 +149,17 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
     if (in.off < 0) return fail(GP_ERR_SHAPE, "instance %d has a negative offset", i);
     if (in.d < 1 || in.d > kMaxD) return fail(GP_ERR_SHAPE, "instance %d has d = %d", i, in.d);
     in.dp = padded_dim(in.d);
-    in.nth = k->kind == GP_SE_ISO ? 3 : in.d + 2;
+    if (k->kind == GP_SE_CHEB) {
+      gp_kernel kk = *k;
+      kk.d = in.d;
+      const int32_t nt = gp_n_theta(&kk);
+      if (nt < 0)
+        return fail(GP_ERR_ARG, "instance %d: n_cheb = %d with d = %d gives more than 64 terms", i,
+                    k->n_cheb, in.d);
+      in.nth = nt;
+    } else {
+      in.nth = k->kind == GP_SE_ISO ? 3 : in.d + 2;
+    }
     in.xoff = b->x_offsets ? b->x_offsets[i] : in.off * in.d;
     if (in.xoff < 0) return fail(GP_ERR_SHAPE, "instance %d has a negative x offset", i);
     (void)xo;
@@ -229,6 +245,23 @@ std::mutex g_mu;
 std::map<void *, std::vector<char>> g_uploaded;  // ws -> descriptor bytes last uploaded
 std::map<void *, GraphEntry> g_graphs;           // ws -> captured trajectory
 
+// One job of an ext chain: MvX / MvP as q = A x or A p, Qf as the force and the two forms of
+// [x | phi] with w = (-1/2, +1/2) into the chain's ext_res.  `hdesc` holds the chain descriptors
+// as uploaded (device pointers); `cp` is the chain's device copy.
+template <typename T>
+gp_status ext_job(const gp_kernel &kk, const InstInfo &in, int job, const char *hdesc, int c,
+                  void *cp, char *pw, size_t pw_bytes, hipStream_t stream) {
+  const HmcChain<T> *hc = (const HmcChain<T> *)hdesc + c;
+  if (job == kJobMvX || job == kJobMvP) {
+    const T *v = job == kJobMvX ? hc->x : hc->p;
+    return gp_kmatvec(&kk, in.n, hc->X, hc->theta, 1, v, 1, nullptr, hc->q, 1, pw, pw_bytes, stream);
+  }
+  HmcChain<T> *dc = (HmcChain<T> *)cp;
+  return gp_quadform_grad(&kk, in.n, hc->X, hc->theta, 2, hc->Z, 2, hc->Z, 2, dc->ext_w,
+                          dc->ext_res, dc->ext_res + in.nth, nullptr, 0, nullptr, 0, pw, pw_bytes,
+                          stream);
+}
+
 }  // namespace
 }  // namespace gpk
 
@@ -239,7 +272,7 @@ extern "C" {
 size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b) {
   std::vector<InstInfo> inst;
   if (collect(k, p, b, inst) != GP_OK) return 0;
-  return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind).total;
+  return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind, k->n_cheb).total;
 }
 
 gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
@@ -254,7 +287,7 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status)
     return fail(GP_ERR_ARG, "X, y, phi, theta, pi, x_warm, H0, H1, accepted and status must be non-NULL");
   const int chains = b->chains_per_inst;
-  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind);
+  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind, k->n_cheb);
   if (!ws || ws_bytes < L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -265,12 +298,12 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
     fill_chains<double>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                        accepted, status, cg_iters, 0, v);
+                        accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
     fill_chains<float>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                       accepted, status, cg_iters, k->prec == GP_BF16X ? 1 : 0, v);
+                       accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
   // chain order for the batched scheduler: largest problems first
@@ -337,29 +370,19 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
         if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
         if (done) break;
         const int dpc = inst[c / chains].dp;
-        if (k->prec == GP_BF16X) {
-          // the job runs as one product pass of the cross-term kernel
+        if (uses_ext(k->prec, k->kind)) {
+          // the job runs as one call of the product entry points
           int job = 0;
           e = hipMemcpyAsync(&job, (char *)cp + off_job, sizeof(int), hipMemcpyDeviceToHost, stream);
           if (e == hipSuccess) e = hipStreamSynchronize(stream);
           if (e != hipSuccess) return hip_fail(e, "plain-mode job read");
           const InstInfo &in = inst[c / chains];
-          const HmcChain<float> *hc = (const HmcChain<float> *)desc.data() + c;
           gp_kernel kk = *k;
           kk.d = in.d;
-          char *pw = w + L.prod;
-          const double *thc = hc->theta;
-          gp_status ps;
-          if (job == kJobMvX || job == kJobMvP) {
-            const float *v = job == kJobMvX ? hc->x : hc->p;
-            ps = gp_kmatvec(&kk, in.n, hc->X, thc, 1, v, 1, nullptr, hc->q, 1, pw, L.prod_bytes,
-                            stream);
-          } else {
-            HmcChain<float> *dc = (HmcChain<float> *)cp;
-            ps = gp_quadform_grad(&kk, in.n, hc->X, thc, 2, hc->Z, 2, hc->Z, 2, dc->ext_w,
-                                  dc->ext_res, dc->ext_res + in.nth, nullptr, 0, nullptr, 0, pw,
-                                  L.prod_bytes, stream);
-          }
+          const gp_status ps = f64 ? ext_job<double>(kk, in, job, desc.data(), c, cp, w + L.prod,
+                                                     L.prod_bytes, stream)
+                                   : ext_job<float>(kk, in, job, desc.data(), c, cp, w + L.prod,
+                                                    L.prod_bytes, stream);
           if (ps != GP_OK) return ps;
         } else {
           e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);

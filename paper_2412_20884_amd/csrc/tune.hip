@@ -106,7 +106,7 @@ using namespace gpk;
 extern "C" {
 
 size_t gp_tune_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
-  if (!k || n < 1 || r < 1) return 0;
+  if (!k || n < 1 || r < 1 || k->kind == GP_SE_CHEB) return 0;
   const size_t es = k->prec == GP_F64 ? 8 : 4;
   const size_t prod = gp_workspace_size(k, n, r);
   if (prod == 0) return 0;
@@ -121,6 +121,8 @@ gp_status gp_tune_products(const gp_kernel *k, int64_t n, int32_t r, int32_t wit
                            void *ws, size_t ws_bytes, hipStream_t stream) {
   clear_error();
   if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
+  if (k->kind == GP_SE_CHEB)
+    return fail(GP_ERR_UNSUPPORTED, "GP_SE_CHEB runs on the GP_SE_ISO kernels: tune those");
   if (n < 1 || r < 1) return fail(GP_ERR_SHAPE, "n and r must be >= 1");
   if (with_grad && r > kMaxRPass) return fail(GP_ERR_SHAPE, "r = %d > %d with gradient", r, kMaxRPass);
   const int32_t nth = gp_n_theta(k);

@@ -14,7 +14,7 @@ import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgpk.so")
 
-ISO, ARD = 0, 1
+ISO, ARD, CHEB = 0, 1, 2
 F64, F32, BF16X = 0, 1, 2
 NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
@@ -37,7 +37,7 @@ class GpkError(RuntimeError):
 
 class Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("prec", ctypes.c_int32), ("d", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("n_cheb", ctypes.c_int32)]
 
 
 class HmcParams(ctypes.Structure):
@@ -135,6 +135,8 @@ def kind_code(kind):
         return ISO
     if kind in (ARD, "ard"):
         return ARD
+    if kind in (CHEB, "cheb"):
+        return CHEB
     raise ValueError(f"unknown kernel kind {kind!r}")
 
 
@@ -150,12 +152,20 @@ def prec_code(dtype, prec=None):
     raise TypeError(f"unsupported dtype {dtype}")
 
 
-def make_kernel(kind, X, prec=None, no_noise=False):
-    return Kernel(kind_code(kind), prec_code(X.dtype, prec), X.shape[1], NO_NOISE if no_noise else 0)
+def make_kernel(kind, X, prec=None, no_noise=False, n_cheb=0):
+    """Kernel description for points X; the Chebyshev-amplitude kernel ("cheb") needs n_cheb."""
+    kc = kind_code(kind)
+    if kc == CHEB and n_cheb < 1:
+        raise ValueError("the Chebyshev-amplitude kernel needs n_cheb >= 1")
+    return Kernel(kc, prec_code(X.dtype, prec), X.shape[1], NO_NOISE if no_noise else 0,
+                  int(n_cheb))
 
 
-def n_theta(kind, d):
-    return 3 if kind_code(kind) == ISO else d + 2
+def n_theta(kind, d, n_cheb=0):
+    kc = kind_code(kind)
+    if kc == CHEB:
+        return int(n_cheb) ** d + 2
+    return 3 if kc == ISO else d + 2
 
 
 def _rowmajor(t, name):
@@ -185,7 +195,8 @@ def _workspace(nbytes, device, ws=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, out=None, ws=None):
+def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, out=None, ws=None,
+            n_cheb=0):
     """(A(theta) + diag(col_shift)) V through gp_kmatvec.  V may be 1-D (one column)."""
     squeeze = V.dim() == 1
     V2 = V[:, None] if squeeze else V
@@ -196,7 +207,7 @@ def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, 
     dev = X.device
     _same(dev, X.dtype, V=V2)
     _same(dev, torch.float64, theta=theta, col_shift=col_shift)
-    k = make_kernel(kind, X, prec, no_noise)
+    k = make_kernel(kind, X, prec, no_noise, n_cheb)
     n, r = X.shape[0], V2.shape[1]
     if out is None:
         out = torch.empty((n, r), dtype=X.dtype, device=dev)
@@ -210,7 +221,7 @@ def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, 
 
 
 def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=True,
-                  want_quad=True, want_AU=False, want_AV=False, ws=None):
+                  want_quad=True, want_AU=False, want_AV=False, ws=None, n_cheb=0, no_noise=False):
     """sum_c w_c u_c^T A v_c: dict with 'grad' (n_theta), 'quad' (R), 'AU', 'AV' as requested."""
     if V is None:
         V = U
@@ -220,9 +231,9 @@ def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=
     dev = X.device
     _same(dev, X.dtype, U=U, V=V)
     _same(dev, torch.float64, theta=theta, w=w)
-    k = make_kernel(kind, X, prec)
+    k = make_kernel(kind, X, prec, no_noise, n_cheb)
     n, r = X.shape[0], U.shape[1]
-    nt = n_theta(kind, X.shape[1])
+    nt = n_theta(kind, X.shape[1], n_cheb)
     grad = torch.empty(nt, dtype=torch.float64, device=dev) if want_grad else None
     quad = torch.empty(r, dtype=torch.float64, device=dev) if want_quad else None
     AU = torch.empty((n, r), dtype=X.dtype, device=dev) if want_AU else None
@@ -244,7 +255,7 @@ def hmc_workspace_size(kernel, params, batch):
 
 def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, d=None,
                  x_offsets=None, u=None, n_steps=20, dt=1e-2, cg_tol=1e-6, cg_maxit=1000,
-                 mode=BATCHED, ws=None, cg_iters=True, prec=None):
+                 mode=BATCHED, ws=None, cg_iters=True, prec=None, n_cheb=0):
     """One HMC trajectory per chain through gp_hmc_leapfrog (packing as in include/gpk.h).
 
     theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, cg_iters).
@@ -259,7 +270,7 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
-    k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0)
+    k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
     prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode))
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
     offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
@@ -332,7 +343,7 @@ def phi_workspace_size(kernel, params, n, r):
 
 
 def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit=2000,
-                lambda_max=None, out=None, ws=None):
+                lambda_max=None, out=None, ws=None, n_cheb=0):
     """phi = A(theta)^{-1/2} xi through gp_phi_refresh.  xi may be 1-D (one column).
 
     Returns dict(phi, status, iters, bounds=(m, M))."""
@@ -345,7 +356,7 @@ def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit
     dev = X.device
     _same(dev, X.dtype, xi=xi2)
     _same(dev, torch.float64, theta=theta)
-    k = make_kernel(kind, X, prec)
+    k = make_kernel(kind, X, prec, n_cheb=n_cheb)
     prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0))
     n, r = X.shape[0], xi2.shape[1]
     if out is None:

@@ -15,9 +15,9 @@ Workloads (shapes and distributions of the five benchmark configurations):
   batched     64 instances, N_b uniform integers in [2048, 32768], d_b in {4, 8, 16},
               X ~ N(0, I_d), ARD SE, l_k log-uniform on [0.3, 3], alpha = 1, sigma^2 = 0.1 (the
               noise variance of the paper's synthetic scaling runs), y = prod_k cos(x_k) +
-              0.1 N(0,1); 8 chains each; 20-step trajectories.
+              0.1 N(0,1); 8 chains each; 20-step trajectories of step 1e-3.
   ard64       N=262,144, X ~ N(0, I_64), ARD SE, l_k log-uniform on [0.5, 8], alpha = 1,
-              sigma^2 = 1e-2; 16 chains x 50 leapfrog steps.
+              sigma^2 = 1e-2; 16 chains x 50 leapfrog steps of step 1e-4.
 """
 from __future__ import annotations
 
@@ -110,7 +110,7 @@ def batched(n_inst=64, chains=8, n_lo=2048, n_hi=32768, dims=(4, 8, 16), n_steps
             "pi": rng(sb, P_PI).standard_normal((chains, len(theta))),
             "u": rng(sb, P_UACC).uniform(size=chains),
         })
-    return {"kind": "ard", "instances": inst, "chains": chains, "dt": 1e-2, "n_steps": n_steps}
+    return {"kind": "ard", "instances": inst, "chains": chains, "dt": 1e-3, "n_steps": n_steps}
 
 
 def ard64(n=262144, chains=16, n_steps=50):
@@ -122,7 +122,7 @@ def ard64(n=262144, chains=16, n_steps=50):
         "xi": rng(s, P_XI).standard_normal((chains, n)),
         "pi": rng(s, P_PI).standard_normal((chains, 66)),
         "u": rng(s, P_UACC).uniform(size=chains),
-        "dt": 1e-2, "n_steps": n_steps, "chains": chains,
+        "dt": 1e-4, "n_steps": n_steps, "chains": chains,
     }
 
 

@@ -36,6 +36,13 @@ def test_status_strings_and_n_theta():
     assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 8, 0))) == 10
     assert L.gp_n_theta(ctypes.byref(gpk.Kernel(7, gpk.F32, 8, 0))) == -1
     assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 65, 0))) == -1
+    # Chebyshev-amplitude kernel: N_cheb^d + 2 hyperparameters, at most 64 terms
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 1, 0, 2))) == 4
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F64, 3, 0, 4))) == 66
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 9))) == -1
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 0))) == -1
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 64, 0, 1))) == 3
+    assert L.gp_n_theta(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 7, 0, 2))) == -1
 
 
 def _kmv(k, n=10, X=1, th=1, r=2, V=4096, ldv=2, out=1 << 20, ldo=2, ws=8, wsb=1 << 30):
@@ -81,7 +88,8 @@ def test_quadform_validation():
     assert q(r=0) == 2
     assert q(r=33) == 2
     assert q(grad=0) == 1
-    assert q(kk=ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, gpk.NO_NOISE))) == 1
+    # GP_NO_NOISE is accepted (the form in K alone): the call gets as far as the workspace check
+    assert q(kk=ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, gpk.NO_NOISE)), wsb=8) == 4
     assert q(AU=4096 + 8) == 1          # AU overlaps U
     assert q(AU=1 << 20, ldau=1) == 2
     assert q(wsb=8) == 4
@@ -119,3 +127,14 @@ def test_tune_table_json_roundtrip(tmp_path):
     gpk.tune_clear()
     L = gpk.lib()
     assert L.gp_tune_load(b"/nonexistent/x.json") == 1
+
+
+def test_cheb_workspace_and_tuner():
+    L = gpk.lib()
+    k = ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 3))
+    se = ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 2, gpk.NO_NOISE, 0))
+    # the Chebyshev path holds the SE workspace plus amplitudes and four scaled n x r blocks
+    assert L.gp_workspace_size(k, 5000, 4) > L.gp_workspace_size(se, 5000, 4) + 4 * 5000 * 4 * 4
+    assert L.gp_workspace_size(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 9)), 5000, 4) == 0
+    assert L.gp_tune_workspace_size(k, 5000, 4) == 0
+    assert L.gp_tune_products(k, 5000, 4, 1, None, 0, None) == 3
