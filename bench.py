@@ -1,6 +1,7 @@
 """Benchmark of the hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-cpu] [--no-ard64]
+                    [--no-precond]
 
 A step is one fused gp_quadform_grad pass over the large3 workload (N = 2^20 points uniform in
 [0,1]^3, isotropic SE kernel l = 0.05, alpha = 1, sigma^2 = 1e-3, 32 N(0,1) auxiliary vectors Z):
@@ -10,8 +11,9 @@ step).  The JSON line also carries the roofline of the dominant kernel (the matr
 kernel), the FP64 oracle timed on a bounded row slab of the same workload on the host cores,
 a sampled parity check of the timed outputs, the batched-vs-plain HMC leapfrog comparison on the
 batched workload (64 instances, 8 chains each, 20-step trajectories) with phi drawn by the
-device Gibbs refresh (timed as its own leg), and the d = 64 workload in the bfloat16
-cross-term precision (product and force-pass rates, one short trajectory).
+device Gibbs refresh (timed as its own leg), the d = 64 workload in the bfloat16 cross-term
+precision (product and force-pass rates, one short trajectory), and plain CG against
+Nystrom-preconditioned CG on the ard8 workload.
 """
 from __future__ import annotations
 
@@ -34,6 +36,34 @@ PEAK_F32_VECTOR = 157.3e12   # fp32 vector peak, FLOP/s
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_mfma_large3_traffic.md")
+KERNEL_SOURCES = ["paper_2412_20884_amd/csrc/pair_mfma.hip", "paper_2412_20884_amd/csrc/pass.h",
+                  "paper_2412_20884_amd/csrc/common.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3 counter summary, or
+    None when the kernel sources have changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def bench_large3(steps, warmup, tune=True, tune_load=None):
@@ -294,6 +324,47 @@ def bench_ard64(n_chain_steps=4):
     return out
 
 
+def bench_precond(rank=200):
+    """Solves A x = y on the ard8 workload (N = 65,536, d = 8, FP32, sigma^2 = 1e-2): plain CG
+    against CG preconditioned by a rank-`rank` randomized Nystrom factor, same tolerance."""
+    import torch
+
+    from paper_2412_20884_amd import gpk, inputs
+
+    dev = "cuda:0"
+    w = inputs.ard8(r=1)
+    n = w["X"].shape[0]
+    X = torch.tensor(w["X"], dtype=torch.float32, device=dev)
+    th = torch.tensor(w["theta"], dtype=torch.float64, device=dev)
+    y = torch.tensor(w["V"][:, 0], dtype=torch.float32, device=dev)
+    om = torch.tensor(inputs.normal_matrix(n, rank, inputs.WORKLOAD_SEEDS["ard8"], inputs.P_XI),
+                      dtype=torch.float32, device=dev)
+    out = {"workload": f"ard8: N={n}, d=8, ARD SE, sigma^2=1e-2, FP32; A x = y to relative residual "
+                       f"1e-6; Nystrom rank {rank}", "rank": rank}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = gpk.pcg_solve(X, th, y, "ard", tol=1e-6, maxit=5000)
+    torch.cuda.synchronize()
+    out["cg"] = {"seconds": time.perf_counter() - t0, "iterations": int(plain["iters"][0]),
+                 "status": int(plain["status"][0])}
+    log(f"precond: plain CG {out['cg']}")
+    t0 = time.perf_counter()
+    U, lam = gpk.nystrom(X, th, om, "ard")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pre = gpk.pcg_solve(X, th, y, "ard", U=U, lam=lam, tol=1e-6, maxit=5000)
+    torch.cuda.synchronize()
+    out["nystrom_pcg"] = {"build_seconds": t_build, "solve_seconds": time.perf_counter() - t0,
+                          "iterations": int(pre["iters"][0]), "status": int(pre["status"][0]),
+                          "lam_top": float(lam[0]), "lam_last": float(lam[-1])}
+    diff = (plain["x"] - pre["x"]).double().norm() / plain["x"].double().norm()
+    out["solution_rel_diff"] = float(diff)
+    out["speedup_total"] = out["cg"]["seconds"] / (t_build + out["nystrom_pcg"]["solve_seconds"])
+    log(f"precond: Nystrom PCG {out['nystrom_pcg']}, speedup {out['speedup_total']:.2f}")
+    return out
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device copy of a known size, run under the same profiler command so its
     FETCH_SIZE / WRITE_SIZE readings calibrate the counters (bytes per counter unit)."""
@@ -321,6 +392,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ard64", action="store_true")
+    ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--tune-load", default=None, help="load a saved tuning table instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -354,7 +426,8 @@ def main():
                                "sigma^2=1e-3, 32 N(0,1) auxiliary vectors; fused A Z + z_c^T A z_c + grad_theta",
                    "N": n, "d": 3, "R": b["r"], "pairs_per_step": n * n},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_F16_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_F16_MFMA, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_F16_MFMA, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "pair_mfma<3,32,1> (fp16 hi/lo split, 3 products per contraction)",
                      "flop_per_pair": FLOP_PER_PAIR,
                      "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR},
@@ -368,6 +441,8 @@ def main():
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset)
     if not args.no_ard64:
         line["ard64_bf16x"] = bench_ard64()
+    if not args.no_precond:
+        line["nystrom_precond"] = bench_precond()
     print(json.dumps(line), flush=True)
 
 

@@ -282,6 +282,54 @@ gp_status gp_phi_refresh(const gp_kernel *k, const gp_phi_params *p, int64_t n, 
                          int64_t ldphi, int32_t *status, int32_t *iters, double *bounds, void *ws,
                          size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Randomized Nystrom preconditioner (Section 3.1 after eq. pex, Section 3.2.3; rank 5 in
+ * Section 4.1 and 500 in Section 4.3): a low-rank factor K ~ U diag(lam) U^T of the kernel
+ * matrix, which through the Woodbury identity gives an approximate inverse of A + lambda I =
+ * K + (sigma^2 + lambda) I for every shift lambda from the same factor.
+ *
+ * gp_nystrom -- U and lam for the Gaussian test matrix omega supplied by the caller:
+ * Q = orth(omega) (Cholesky-QR, twice), Y = K Q, nu = sqrt(n) eps |Y|_F, C^T C = Q^T (Y + nu Q),
+ * B = (Y + nu Q) C^{-1} = U S V^T, lam = max(0, S^2 - nu) (descending).  The l x l Cholesky
+ * factorisations and the eigendecomposition of B^T B run on the host in double; the call
+ * synchronises `stream`.
+ *   omega   device, n x rank, contiguous (leading dimension rank), kernel precision
+ *   U       device out, n x rank, contiguous, kernel precision (orthonormal columns)
+ *   lam     device out, double[rank]
+ *   rank    1..min(n, 512)
+ */
+size_t gp_nystrom_workspace_size(const gp_kernel *k, int64_t n, int32_t rank);
+gp_status gp_nystrom(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                     int32_t rank, const void *omega, void *U, double *lam, void *ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+enum {
+  GP_CG_MAXIT = 1,     /* the column had not reached tol after maxit iterations */
+  GP_CG_NONFINITE = 2  /* a NaN or infinity appeared (or p^T A p <= 0) */
+};
+
+/*
+ * gp_pcg_solve -- (A(theta) + lambda_c I) x_c = b_c for r columns at once by conjugate
+ * gradients, preconditioned with P^{-1} = U diag((lam_rank + mu_c) / (lam + mu_c)) U^T +
+ * (I - U U^T), mu_c = sigma^2 + lambda_c, when rank > 0 (plain CG when rank = 0).  These are
+ * the solves of eq. (xtheta) (lambda = 0) and of the pole expansion eq. (pex) (lambda = the
+ * shifts).  Each column stops at |b_c - (A + lambda_c) x_c| <= tol |b_c| (recurrence residual).
+ * The host checks convergence every few iterations; the call synchronises `stream`.
+ *   B        device, n x r (r in 1..32), leading dimension ldb >= r
+ *   x        device, n x r, leading dimension ldx >= r: start on entry, solution on return
+ *   col_shift device double[r] or NULL (all 0)
+ *   U, lam   the gp_nystrom factor (U n x rank contiguous), or NULL with rank = 0
+ *   status   device int32[r] or NULL: GP_CG_* bits per column (0 = converged)
+ *   iters    device int32[r] or NULL: iterations used per column
+ * GP_NO_NOISE is rejected.
+ */
+size_t gp_pcg_workspace_size(const gp_kernel *k, int64_t n, int32_t r, int32_t rank);
+gp_status gp_pcg_solve(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                       int32_t r, const void *B, int64_t ldb, void *x, int64_t ldx,
+                       const double *col_shift, int32_t rank, const void *U, const double *lam,
+                       double tol, int32_t maxit, int32_t *status, int32_t *iters, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

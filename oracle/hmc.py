@@ -119,3 +119,38 @@ def trajectory(X, kind, y, phi, theta0, pi0, dt, n_steps, u=None, prior=None, gr
         "H1": H1,
         "accepted": ok,
     }
+
+
+# ---- implicit midpoint integrator (Section 3.2.3) ------------------------------------------
+
+
+def implicit_midpoint_step(force_fn, theta0, pi0, dt, tol=1e-14, maxit=10000):
+    """One step of the 1-stage Gauss-Legendre (implicit midpoint) integrator, eq. (implicitsystem):
+        theta_1 = theta_0 + dt (pi_0 + pi_1) / 2,   pi_1 = pi_0 - dt F((theta_0 + theta_1) / 2).
+    Eliminating theta_1 and pi_1 leaves the midpoint m = (theta_0 + theta_1)/2 as the fixed point of
+        m = theta_0 + dt/2 pi_0 - dt^2/4 F(m),
+    iterated here until the update is below tol (relative); raises if it does not converge.
+    """
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    pi0 = np.asarray(pi0, dtype=np.float64)
+    m = theta0 + 0.5 * dt * pi0
+    for _ in range(maxit):
+        m_new = theta0 + 0.5 * dt * pi0 - 0.25 * dt * dt * np.asarray(force_fn(m), dtype=np.float64)
+        done = np.max(np.abs(m_new - m)) <= tol * (1.0 + np.max(np.abs(m_new)))
+        m = m_new
+        if done:
+            pi1 = pi0 - dt * np.asarray(force_fn(m), dtype=np.float64)
+            return 2.0 * m - theta0, pi1
+    raise RuntimeError("implicit midpoint fixed point did not converge")
+
+
+def implicit_midpoint(X, kind, y, phi, theta0, pi0, dt, n_steps, grad_prior=None, tol=1e-14):
+    """[implicit midpoint]^{n_steps}(theta0, pi0) with the exact-solve force: at the solution the
+    third equation of (implicitsystem), A(m) x = y, holds exactly because F is evaluated at
+    x = A(m)^{-1} y (Cholesky)."""
+    theta = np.array(theta0, dtype=np.float64)
+    pi = np.array(pi0, dtype=np.float64)
+    for _ in range(n_steps):
+        theta, pi = implicit_midpoint_step(lambda m: force(X, m, kind, y, phi, grad_prior), theta, pi,
+                                           dt, tol=tol)
+    return theta, pi

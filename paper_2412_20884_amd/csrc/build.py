@@ -29,7 +29,8 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "pair_valu_f32.hip", "pair_valu_f64.hip", "pair_mfma.hip", "hmc.hip",
-           "hmc_f32.hip", "hmc_f64.hip", "tune.hip", "pair_xm.hip", "poles.hip", "cheb.hip"]
+           "hmc_f32.hip", "hmc_f64.hip", "tune.hip", "pair_xm.hip", "poles.hip", "cheb.hip",
+           "nystrom.hip"]
 
 
 def _compile(src):

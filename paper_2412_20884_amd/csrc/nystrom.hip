@@ -1,0 +1,739 @@
+// Randomized Nystrom preconditioner (Section 3.1 after eq. pex; Section 3.2.3; rank 5 in
+// Section 4.1, rank 500 in Section 4.3) and batched preconditioned conjugate gradients.
+//
+// Nystrom factor, in the order of the randomized construction the paper uses (Frangella, Tropp
+// and Udell), for an n x l Gaussian test matrix Omega supplied by the caller:
+//     Q = orth(Omega)            Cholesky-QR applied twice (Gram on the device, l x l Cholesky on
+//                                the host in double)
+//     Y = K Q                    gp_kmatvec with GP_NO_NOISE, l right-hand sides
+//     nu = sqrt(n) eps |Y|_F     Y_nu = Y + nu Q
+//     C^T C = Q^T Y_nu,  B = Y_nu C^{-1}
+//     B = U S V^T                from the l x l eigendecomposition of B^T B (cyclic Jacobi on the
+//                                host): U = B V S^{-1}
+//     lam = max(0, S^2 - nu),    K ~ U diag(lam) U^T.
+// Preconditioner for A + lambda I = K + mu I (mu = sigma^2 + lambda, so one factor serves every
+// shift through the Woodbury identity):
+//     P^{-1} r = r + U ((lam_l + mu) / (lam + mu) - 1) U^T r.
+// The tall-skinny products (Gram matrices A^T B and right multiplications A M) run in the
+// kernels below with double accumulation and fixed-order chunk sums.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "gpk.h"
+#include "vecops.h"
+
+namespace gpk {
+
+gp_status fail(gp_status st, const char *fmt, ...);
+void clear_error();
+gp_status hip_fail(hipError_t e, const char *where);
+
+namespace {
+
+constexpr int kRankMax = 512;
+constexpr int kPcgMaxR = 32;
+constexpr int kCheckEvery = 4;
+constexpr int kGT = 32;          // Gram output tile
+constexpr int kMR = 64, kMC = 32, kMK = 32;  // right-multiplication tiles
+
+// ---- tall-skinny kernels --------------------------------------------------------------------
+
+// part[chunk][i][j] = sum over the chunk's rows of A[row][i] B[row][j]; i < l1, j < l2.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial(int64_t n, int l1, const T *A, int64_t lda,
+                                                    int l2, const T *B, int64_t ldb,
+                                                    int64_t rows_per_chunk, double *part) {
+  __shared__ double sa[kGT][kGT + 1], sb[kGT][kGT + 1];
+  const int t = threadIdx.x;
+  const int tiles_j = (l2 + kGT - 1) / kGT;
+  const int i0 = (blockIdx.y / tiles_j) * kGT, j0 = (blockIdx.y % tiles_j) * kGT;
+  const int ii = t / 8, jj = (t % 8) * 4;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(n, r0 + rows_per_chunk);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0; rb < r1; rb += kGT) {
+    for (int e = t; e < kGT * kGT; e += 256) {
+      const int rr = e / kGT, cc = e % kGT;
+      const int64_t row = rb + rr;
+      sa[rr][cc] = (row < r1 && i0 + cc < l1) ? (double)A[row * lda + i0 + cc] : 0.0;
+      sb[rr][cc] = (row < r1 && j0 + cc < l2) ? (double)B[row * ldb + j0 + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < kGT; ++rr) {
+      const double a = sa[rr][ii];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += a * sb[rr][jj + q];
+    }
+    __syncthreads();
+  }
+  double *out = part + (int64_t)blockIdx.x * l1 * l2;
+  if (i0 + ii < l1)
+    for (int q = 0; q < 4; ++q)
+      if (j0 + jj + q < l2) out[(int64_t)(i0 + ii) * l2 + j0 + jj + q] = acc[q];
+}
+
+__global__ void gram_final(int nchunk, int64_t m, const double *part, double *G) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * m + e];
+  G[e] = s;
+}
+
+// out[row][c] = Cin[row][c] (if given) + sum_k A[row][k] M[k][c]; M is l x m, row-major, double.
+template <typename T>
+__global__ __launch_bounds__(256) void right_mul(int64_t n, int l, const T *A, int64_t lda,
+                                                 const double *M, int m, const T *Cin,
+                                                 int64_t ldc, T *out, int64_t ldo) {
+  __shared__ double sa[kMR][kMK + 1], sm[kMK][kMC + 1];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * kMR;
+  const int c0 = blockIdx.y * kMC;
+  const int rr = t / 4, cc = (t % 4) * 8;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k0 = 0; k0 < l; k0 += kMK) {
+    for (int e = t; e < kMR * kMK; e += 256) {
+      const int a = e / kMK, b = e % kMK;
+      const int64_t row = row0 + a;
+      sa[a][b] = (row < n && k0 + b < l) ? (double)A[row * lda + k0 + b] : 0.0;
+    }
+    for (int e = t; e < kMK * kMC; e += 256) {
+      const int a = e / kMC, b = e % kMC;
+      sm[a][b] = (k0 + a < l && c0 + b < m) ? M[(int64_t)(k0 + a) * m + c0 + b] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kMK; ++k) {
+      const double a = sa[rr][k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += a * sm[k][cc + q];
+    }
+    __syncthreads();
+  }
+  const int64_t row = row0 + rr;
+  if (row < n)
+    for (int q = 0; q < 8; ++q) {
+      const int c = c0 + cc + q;
+      if (c < m) {
+        const double base = Cin ? (double)Cin[row * ldc + c] : 0.0;
+        out[row * ldo + c] = (T)(base + acc[q]);
+      }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_partial(int64_t m, const T *a, double *part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
+    const double v = (double)a[e];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void axpy_inplace(int64_t m, double a, const T *x, T *y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < m) y[e] = (T)((double)y[e] + a * (double)x[e]);
+}
+
+// ---- host dense linear algebra (l x l, double, row-major) ----------------------------------
+
+// G = C^T C with C upper triangular; false if G is not numerically positive definite.
+bool chol_upper(const std::vector<double> &G, int l, std::vector<double> &C) {
+  C.assign((size_t)l * l, 0.0);
+  for (int j = 0; j < l; ++j) {
+    double s = G[(size_t)j * l + j];
+    for (int k = 0; k < j; ++k) s -= C[(size_t)k * l + j] * C[(size_t)k * l + j];
+    if (!(s > 0.0)) return false;
+    const double d = sqrt(s);
+    C[(size_t)j * l + j] = d;
+    for (int i = j + 1; i < l; ++i) {
+      double t = G[(size_t)j * l + i];
+      for (int k = 0; k < j; ++k) t -= C[(size_t)k * l + j] * C[(size_t)k * l + i];
+      C[(size_t)j * l + i] = t / d;
+    }
+  }
+  return true;
+}
+
+// Inverse of an upper-triangular matrix (upper triangular).
+void inv_upper(const std::vector<double> &C, int l, std::vector<double> &Ci) {
+  Ci.assign((size_t)l * l, 0.0);
+  for (int j = 0; j < l; ++j) {
+    Ci[(size_t)j * l + j] = 1.0 / C[(size_t)j * l + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += C[(size_t)i * l + k] * Ci[(size_t)k * l + j];
+      Ci[(size_t)i * l + j] = -s / C[(size_t)i * l + i];
+    }
+  }
+}
+
+// Eigenvalues (descending) and eigenvectors (columns of V) of a symmetric matrix by cyclic
+// Jacobi rotations.
+void jacobi_eig(std::vector<double> S, int l, std::vector<double> &ev, std::vector<double> &V) {
+  V.assign((size_t)l * l, 0.0);
+  for (int i = 0; i < l; ++i) V[(size_t)i * l + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < l; ++i)
+      for (int j = 0; j < l; ++j) {
+        const double v = S[(size_t)i * l + j] * S[(size_t)i * l + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < l - 1; ++p)
+      for (int q = p + 1; q < l; ++q) {
+        const double apq = S[(size_t)p * l + q];
+        if (fabs(apq) < 1e-300) continue;
+        const double app = S[(size_t)p * l + p], aqq = S[(size_t)q * l + q];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < l; ++k) {  // rows p, q
+          const double a = S[(size_t)p * l + k], b = S[(size_t)q * l + k];
+          S[(size_t)p * l + k] = c * a - s * b;
+          S[(size_t)q * l + k] = s * a + c * b;
+        }
+        for (int k = 0; k < l; ++k) {  // columns p, q
+          const double a = S[(size_t)k * l + p], b = S[(size_t)k * l + q];
+          S[(size_t)k * l + p] = c * a - s * b;
+          S[(size_t)k * l + q] = s * a + c * b;
+          const double va = V[(size_t)k * l + p], vb = V[(size_t)k * l + q];
+          V[(size_t)k * l + p] = c * va - s * vb;
+          V[(size_t)k * l + q] = s * va + c * vb;
+        }
+      }
+  }
+  std::vector<int> idx(l);
+  for (int i = 0; i < l; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return S[(size_t)a * l + a] > S[(size_t)b * l + b]; });
+  std::vector<double> V2((size_t)l * l);
+  ev.resize(l);
+  for (int j = 0; j < l; ++j) {
+    ev[j] = S[(size_t)idx[j] * l + idx[j]];
+    for (int i = 0; i < l; ++i) V2[(size_t)i * l + j] = V[(size_t)i * l + idx[j]];
+  }
+  V = V2;
+}
+
+// ---- workspace helpers ------------------------------------------------------------------------
+
+int gram_chunks(int64_t n) {
+  int64_t c = (n + 4095) / 4096;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, c));
+}
+
+struct Gram {
+  int nchunk;
+  int64_t rows_per_chunk;
+};
+
+Gram gram_plan(int64_t n) {
+  Gram g;
+  g.nchunk = gram_chunks(n);
+  g.rows_per_chunk = (n + g.nchunk - 1) / g.nchunk;
+  g.nchunk = (int)((n + g.rows_per_chunk - 1) / g.rows_per_chunk);
+  return g;
+}
+
+template <typename T>
+hipError_t gram(int64_t n, int l1, const T *A, int64_t lda, int l2, const T *B, int64_t ldb,
+                double *part, double *G, hipStream_t s) {
+  const Gram g = gram_plan(n);
+  const int tiles = ((l1 + kGT - 1) / kGT) * ((l2 + kGT - 1) / kGT);
+  gram_partial<T><<<dim3((unsigned)g.nchunk, (unsigned)tiles), 256, 0, s>>>(n, l1, A, lda, l2, B, ldb,
+                                                                           g.rows_per_chunk, part);
+  const int64_t m = (int64_t)l1 * l2;
+  gram_final<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(g.nchunk, m, part, G);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rmul(int64_t n, int l, const T *A, int64_t lda, const double *M, int m, const T *Cin,
+                int64_t ldc, T *out, int64_t ldo, hipStream_t s) {
+  right_mul<T><<<dim3((unsigned)((n + kMR - 1) / kMR), (unsigned)((m + kMC - 1) / kMC)), 256, 0, s>>>(
+      n, l, A, lda, M, m, Cin, ldc, out, ldo);
+  return hipGetLastError();
+}
+
+gp_status to_host(std::vector<double> &h, const double *d, size_t m, hipStream_t s) {
+  h.resize(m);
+  hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(double) * m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? GP_OK : hip_fail(e, "device -> host");
+}
+
+gp_status to_dev(double *d, const std::vector<double> &h, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is a local of the caller
+  return e == hipSuccess ? GP_OK : hip_fail(e, "host -> device");
+}
+
+struct NysLayout {
+  size_t prod, prod_bytes, q, y, w, part, G, M, ss, total;
+};
+
+gp_kernel no_noise_of(const gp_kernel *k) {
+  gp_kernel kk = *k;
+  kk.flags |= GP_NO_NOISE;
+  return kk;
+}
+
+NysLayout nys_layout(const gp_kernel *k, int64_t n, int l) {
+  NysLayout L;
+  const size_t es = k->prec == GP_F64 ? 8 : 4;
+  const gp_kernel kk = no_noise_of(k);
+  size_t o = 0;
+  L.prod = o;
+  L.prod_bytes = gp_workspace_size(&kk, n, l);
+  o += align256(L.prod_bytes);
+  L.q = o;
+  o += align256(es * n * l);
+  L.y = o;
+  o += align256(es * n * l);
+  L.w = o;
+  o += align256(es * n * l);
+  L.part = o;
+  o += align256(sizeof(double) * (size_t)gram_plan(n).nchunk * l * l);
+  L.G = o;
+  o += align256(sizeof(double) * l * l);
+  L.M = o;
+  o += align256(sizeof(double) * l * l);
+  L.ss = o;
+  o += align256(sizeof(double) * 1024);
+  L.total = o;
+  return L;
+}
+
+// Q = W R^{-1}, R from the Cholesky factor of W^T W (one Cholesky-QR step).
+template <typename T>
+gp_status cholqr_step(int64_t n, int l, const T *W, T *Q, const NysLayout &L, char *w,
+                      hipStream_t s) {
+  double *part = (double *)(w + L.part), *G = (double *)(w + L.G), *M = (double *)(w + L.M);
+  hipError_t e = gram<T>(n, l, W, l, l, W, l, part, G, s);
+  if (e != hipSuccess) return hip_fail(e, "Gram");
+  std::vector<double> hG, C, Ci;
+  gp_status st = to_host(hG, G, (size_t)l * l, s);
+  if (st) return st;
+  if (!chol_upper(hG, l, C)) return fail(GP_ERR_ARG, "the test matrix is rank deficient");
+  inv_upper(C, l, Ci);
+  st = to_dev(M, Ci, s);
+  if (st) return st;
+  e = rmul<T>(n, l, W, l, M, l, nullptr, 0, Q, l, s);
+  return e == hipSuccess ? GP_OK : hip_fail(e, "right multiplication");
+}
+
+template <typename T>
+gp_status run_nystrom(const gp_kernel *k, int64_t n, const void *X, const double *theta, int l,
+                      const T *omega, T *U, double *lam, char *w, const NysLayout &L,
+                      hipStream_t s) {
+  T *Q = (T *)(w + L.q), *Y = (T *)(w + L.y), *W = (T *)(w + L.w);
+  double *part = (double *)(w + L.part), *G = (double *)(w + L.G), *M = (double *)(w + L.M);
+  // Q = orth(Omega): Cholesky-QR twice
+  gp_status st = cholqr_step<T>(n, l, omega, W, L, w, s);
+  if (st) return st;
+  st = cholqr_step<T>(n, l, W, Q, L, w, s);
+  if (st) return st;
+  // Y = K Q
+  const gp_kernel kk = no_noise_of(k);
+  st = gp_kmatvec(&kk, n, X, theta, l, Q, l, nullptr, Y, l, w + L.prod, L.prod_bytes, s);
+  if (st) return st;
+  // nu = sqrt(n) eps |Y|_F, Y += nu Q
+  const int64_t m = n * l;
+  const int sb = (int)std::min<int64_t>(1024, (m + 255) / 256);
+  sumsq_partial<T><<<sb, 256, 0, s>>>(m, Y, (double *)(w + L.ss));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "norm");
+  std::vector<double> hs;
+  st = to_host(hs, (const double *)(w + L.ss), sb, s);
+  if (st) return st;
+  double ss = 0.0;
+  for (int b = 0; b < sb; ++b) ss += hs[b];
+  const double eps = k->prec == GP_F64 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  const double nu = sqrt((double)n) * eps * sqrt(ss);
+  axpy_inplace<T><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, nu, Q, Y);
+  // C^T C = Q^T Y_nu (symmetrised), B = Y_nu C^{-1} into W
+  e = gram<T>(n, l, Q, l, l, Y, l, part, G, s);
+  if (e != hipSuccess) return hip_fail(e, "Gram");
+  std::vector<double> hG, C, Ci;
+  st = to_host(hG, G, (size_t)l * l, s);
+  if (st) return st;
+  for (int i = 0; i < l; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double a = 0.5 * (hG[(size_t)i * l + j] + hG[(size_t)j * l + i]);
+      hG[(size_t)i * l + j] = a;
+      hG[(size_t)j * l + i] = a;
+    }
+  if (!chol_upper(hG, l, C)) return fail(GP_ERR_ARG, "Q^T (K + nu I) Q is not positive definite");
+  inv_upper(C, l, Ci);
+  st = to_dev(M, Ci, s);
+  if (st) return st;
+  e = rmul<T>(n, l, Y, l, M, l, nullptr, 0, W, l, s);
+  if (e != hipSuccess) return hip_fail(e, "right multiplication");
+  // B^T B = V S^2 V^T, U = B V S^{-1}, lam = max(0, S^2 - nu)
+  e = gram<T>(n, l, W, l, l, W, l, part, G, s);
+  if (e != hipSuccess) return hip_fail(e, "Gram");
+  st = to_host(hG, G, (size_t)l * l, s);
+  if (st) return st;
+  std::vector<double> ev, V;
+  jacobi_eig(hG, l, ev, V);
+  std::vector<double> hM((size_t)l * l), hl(l);
+  for (int j = 0; j < l; ++j) {
+    const double s2 = ev[j] > 0.0 ? ev[j] : 0.0;
+    const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+    for (int i = 0; i < l; ++i) hM[(size_t)i * l + j] = V[(size_t)i * l + j] * inv;
+    hl[j] = std::max(0.0, s2 - nu);
+  }
+  st = to_dev(M, hM, s);
+  if (st) return st;
+  e = rmul<T>(n, l, W, l, M, l, nullptr, 0, U, l, s);
+  if (e != hipSuccess) return hip_fail(e, "right multiplication");
+  return to_dev(lam, hl, s);
+}
+
+// ---- preconditioned CG ------------------------------------------------------------------------
+
+struct PcgCol {
+  double rz, bb, a, beta;
+  int32_t done, iters, status, pad;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_residual(int64_t n, int r, VecGrid g, const T *B,
+                                                    int64_t ldb, const T *q, T *rv, double *part) {
+  __shared__ double sh[kThreads];
+  const int t = threadIdx.x, c = t % r, l = t / r;
+  double acc = 0.0;
+  if (l < g.rps) {
+    const int64_t i1 = min(n, (int64_t)(blockIdx.x + 1) * g.rows_per_block);
+    for (int64_t i = (int64_t)blockIdx.x * g.rows_per_block + l; i < i1; i += g.rps) {
+      const double b = (double)B[i * ldb + c];
+      rv[i * r + c] = (T)(b - (double)q[i * r + c]);
+      acc += b * b;
+    }
+  }
+  block_column_sum(acc, sh, r, g.rps, part);
+}
+
+// part = per-column partial sums of a . b
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_dot(int64_t n, int r, VecGrid g, const T *a, const T *b,
+                                               double *part) {
+  __shared__ double sh[kThreads];
+  const int t = threadIdx.x, c = t % r, l = t / r;
+  double acc = 0.0;
+  if (l < g.rps) {
+    const int64_t i1 = min(n, (int64_t)(blockIdx.x + 1) * g.rows_per_block);
+    for (int64_t i = (int64_t)blockIdx.x * g.rows_per_block + l; i < i1; i += g.rps)
+      acc += (double)a[i * r + c] * (double)b[i * r + c];
+  }
+  block_column_sum(acc, sh, r, g.rps, part);
+}
+
+// x += a p, r -= a q for live columns; partial sums of the new r . r
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_update(int64_t n, int r, VecGrid g, const PcgCol *col,
+                                                  const T *p, const T *q, T *x, int64_t ldx, T *rv,
+                                                  double *part) {
+  __shared__ double sh[kThreads];
+  const int t = threadIdx.x, c = t % r, l = t / r;
+  double acc = 0.0;
+  if (l < g.rps && !col[c].done) {
+    const double a = col[c].a;
+    const int64_t i1 = min(n, (int64_t)(blockIdx.x + 1) * g.rows_per_block);
+    for (int64_t i = (int64_t)blockIdx.x * g.rows_per_block + l; i < i1; i += g.rps) {
+      x[i * ldx + c] = (T)((double)x[i * ldx + c] + a * (double)p[i * r + c]);
+      const T rn = (T)((double)rv[i * r + c] - a * (double)q[i * r + c]);
+      rv[i * r + c] = rn;
+      acc += (double)rn * (double)rn;
+    }
+  }
+  block_column_sum(acc, sh, r, g.rps, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_direction(int64_t n, int r, VecGrid g, const PcgCol *col,
+                                                     const T *z, T *p, int first) {
+  const int t = threadIdx.x, c = t % r, l = t / r;
+  if (l >= g.rps || col[c].done) return;
+  const double beta = first ? 0.0 : col[c].beta;
+  const int64_t i1 = min(n, (int64_t)(blockIdx.x + 1) * g.rows_per_block);
+  for (int64_t i = (int64_t)blockIdx.x * g.rows_per_block + l; i < i1; i += g.rps)
+    p[i * r + c] = (T)((double)z[i * r + c] + (first ? 0.0 : beta * (double)p[i * r + c]));
+}
+
+// M[k][c] = ((lam_l + mu_c) / (lam_k + mu_c) - 1) t[k][c], mu_c = sigma^2 + shift_c
+__global__ void pcg_prec_scale(int l, int r, const double *lam, const double *theta, int nth,
+                               const double *shift, const double *tkc, double *M) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= l * r) return;
+  const int kk = e / r, c = e % r;
+  const double mu = exp(theta[nth - 1]) + (shift ? shift[c] : 0.0);
+  M[e] = ((lam[l - 1] + mu) / (lam[kk] + mu) - 1.0) * tkc[e];
+}
+
+// Column scalars.  stage 0: bb, rr from part0 / part1 (set-up); stage 1: a = rz / (p.q);
+// stage 2: convergence on r.r; stage 3: beta from the new r.z.
+__global__ void pcg_scalars(int stage, int r, int64_t blocks, const double *part, double tol,
+                            int it, PcgCol *col, int32_t *remaining) {
+  __shared__ double red[kThreads];
+  __shared__ int32_t left;
+  if (threadIdx.x == 0) left = 0;
+  __syncthreads();
+  for (int c = 0; c < r; ++c) {
+    const double v = column_total(part, blocks, r, c, red);
+    if (threadIdx.x == 0) {
+      PcgCol s = col[c];
+      if (stage == 0) {
+        s.bb = v;
+        s.done = 0;
+        s.iters = 0;
+        s.status = isfinite(v) ? 0 : GP_CG_NONFINITE;
+        s.rz = 0.0;
+        s.a = 0.0;
+        s.beta = 0.0;
+        s.pad = 0;
+      } else if (!s.done) {
+        if (stage == 1) {
+          s.a = s.rz / v;
+          if (!(isfinite(s.a) && v > 0.0)) {
+            s.status |= GP_CG_NONFINITE;
+            s.done = 1;
+          }
+        } else if (stage == 2) {
+          if (!isfinite(v)) {
+            s.status |= GP_CG_NONFINITE;
+            s.done = 1;
+          } else if (v <= tol * tol * s.bb) {
+            s.done = 1;
+            s.iters = it;
+          }
+        } else if (stage == 3) {
+          s.beta = v / s.rz;
+          s.rz = v;
+          if (!isfinite(s.beta)) {
+            s.status |= GP_CG_NONFINITE;
+            s.done = 1;
+          }
+        } else if (stage == 4) {  // initial r . z
+          s.rz = v;
+        }
+      }
+      left += 1 - s.done;
+      col[c] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && remaining) *remaining = left;
+}
+
+__global__ void pcg_finish(int r, int maxit, const PcgCol *col, int32_t *status, int32_t *iters) {
+  const int c = threadIdx.x;
+  if (c >= r) return;
+  const PcgCol s = col[c];
+  if (status) status[c] = s.status | (s.done ? 0 : GP_CG_MAXIT);
+  if (iters) iters[c] = s.done ? s.iters : maxit;
+}
+
+template <typename T>
+__global__ void copy_block(int64_t n, int r, const T *a, T *b) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n * r) b[e] = a[e];
+}
+
+struct PcgLayout {
+  size_t prod, prod_bytes, rv, zv, pv, qv, part, gpart, tkc, M, col, remaining, total;
+};
+
+PcgLayout pcg_layout(const gp_kernel *k, int64_t n, int r, int rank) {
+  PcgLayout L;
+  const size_t es = k->prec == GP_F64 ? 8 : 4;
+  size_t o = 0;
+  L.prod = o;
+  L.prod_bytes = gp_workspace_size(k, n, r);
+  o += align256(L.prod_bytes);
+  L.rv = o;
+  o += align256(es * n * r);
+  L.zv = o;
+  o += align256(es * n * r);
+  L.pv = o;
+  o += align256(es * n * r);
+  L.qv = o;
+  o += align256(es * n * r);
+  L.part = o;
+  o += align256(sizeof(double) * kVecBlocksMax * r);
+  L.gpart = o;
+  o += align256(sizeof(double) * (size_t)gram_plan(n).nchunk * std::max(rank, 1) * r);
+  L.tkc = o;
+  o += align256(sizeof(double) * std::max(rank, 1) * r);
+  L.M = o;
+  o += align256(sizeof(double) * std::max(rank, 1) * r);
+  L.col = o;
+  o += align256(sizeof(PcgCol) * r);
+  L.remaining = o;
+  o += 256;
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+gp_status run_pcg(const gp_kernel *k, int64_t n, const void *X, const double *theta, int r,
+                  const T *B, int64_t ldb, T *x, int64_t ldx, const double *shift, int rank,
+                  const T *U, const double *lam, double tol, int maxit, int32_t *status,
+                  int32_t *iters, char *w, const PcgLayout &L, hipStream_t s) {
+  T *rv = (T *)(w + L.rv), *zv = (T *)(w + L.zv), *pv = (T *)(w + L.pv), *qv = (T *)(w + L.qv);
+  double *part = (double *)(w + L.part);
+  PcgCol *col = (PcgCol *)(w + L.col);
+  int32_t *remaining = (int32_t *)(w + L.remaining);
+  const int nth = gp_n_theta(k);
+  const VecGrid g = vec_grid(n, r);
+  const unsigned vb = (unsigned)g.blocks;
+  const unsigned eb = (unsigned)((n * r + 255) / 256);
+  auto precond = [&]() -> gp_status {  // z = P^{-1} r
+    hipError_t e;
+    if (rank == 0) {
+      copy_block<T><<<eb, 256, 0, s>>>(n, r, rv, zv);
+      e = hipGetLastError();
+    } else {
+      double *tkc = (double *)(w + L.tkc), *M = (double *)(w + L.M);
+      e = gram<T>(n, rank, U, rank, r, rv, r, (double *)(w + L.gpart), tkc, s);
+      if (e == hipSuccess) {
+        pcg_prec_scale<<<(unsigned)((rank * r + 255) / 256), 256, 0, s>>>(rank, r, lam, theta, nth,
+                                                                          shift, tkc, M);
+        e = rmul<T>(n, rank, U, rank, M, r, rv, r, zv, r, s);
+      }
+    }
+    return e == hipSuccess ? GP_OK : hip_fail(e, "preconditioner");
+  };
+  // r = b - (A + shift) x, |b|^2
+  gp_status st = gp_kmatvec(k, n, X, theta, r, x, ldx, shift, qv, r, w + L.prod, L.prod_bytes, s);
+  if (st) return st;
+  pcg_residual<T><<<vb, 256, 0, s>>>(n, r, g, B, ldb, qv, rv, part);
+  pcg_scalars<<<1, 256, 0, s>>>(0, r, g.blocks, part, tol, 0, col, nullptr);
+  pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, rv, part);
+  pcg_scalars<<<1, 256, 0, s>>>(2, r, g.blocks, part, tol, 0, col, remaining);
+  st = precond();
+  if (st) return st;
+  pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, zv, part);
+  pcg_scalars<<<1, 256, 0, s>>>(4, r, g.blocks, part, tol, 0, col, nullptr);
+  pcg_direction<T><<<vb, 256, 0, s>>>(n, r, g, col, zv, pv, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "PCG set-up");
+  for (int it = 1; it <= maxit; ++it) {
+    if ((it - 1) % kCheckEvery == 0) {
+      int32_t left = 0;
+      e = hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "convergence check");
+      if (left == 0) break;
+    }
+    st = gp_kmatvec(k, n, X, theta, r, pv, r, shift, qv, r, w + L.prod, L.prod_bytes, s);
+    if (st) return st;
+    pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, pv, qv, part);
+    pcg_scalars<<<1, 256, 0, s>>>(1, r, g.blocks, part, tol, it, col, nullptr);
+    pcg_update<T><<<vb, 256, 0, s>>>(n, r, g, col, pv, qv, x, ldx, rv, part);
+    pcg_scalars<<<1, 256, 0, s>>>(2, r, g.blocks, part, tol, it, col, remaining);
+    st = precond();
+    if (st) return st;
+    pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, zv, part);
+    pcg_scalars<<<1, 256, 0, s>>>(3, r, g.blocks, part, tol, it, col, nullptr);
+    pcg_direction<T><<<vb, 256, 0, s>>>(n, r, g, col, zv, pv, 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "PCG iteration");
+  }
+  pcg_finish<<<1, 64, 0, s>>>(r, maxit, col, status, iters);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? GP_OK : hip_fail(e, "PCG finish");
+}
+
+bool ranges_overlap(const void *a, int64_t rows, int64_t lda, int cols, const void *b, int64_t ldb,
+                    int bcols, size_t es) {
+  const char *a0 = (const char *)a, *b0 = (const char *)b;
+  const char *a1 = a0 + ((rows - 1) * lda + cols) * (int64_t)es;
+  const char *b1 = b0 + ((rows - 1) * ldb + bcols) * (int64_t)es;
+  return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+}  // namespace gpk
+
+using namespace gpk;
+
+extern "C" {
+
+size_t gp_nystrom_workspace_size(const gp_kernel *k, int64_t n, int32_t rank) {
+  if (gp_n_theta(k) < 0 || n < 1 || rank < 1 || rank > kRankMax || rank > n) return 0;
+  return nys_layout(k, n, rank).total;
+}
+
+gp_status gp_nystrom(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                     int32_t rank, const void *omega, void *U, double *lam, void *ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  if (gp_n_theta(k) < 0) return fail(GP_ERR_ARG, "invalid kernel description");
+  if (n < 1) return fail(GP_ERR_SHAPE, "n = %lld < 1", (long long)n);
+  if (rank < 1 || rank > kRankMax || rank > n)
+    return fail(GP_ERR_SHAPE, "rank = %d outside 1..min(n, %d)", rank, kRankMax);
+  if (!X || !theta || !omega || !U || !lam)
+    return fail(GP_ERR_ARG, "X, theta, omega, U and lam must be non-NULL");
+  const size_t es = k->prec == GP_F64 ? 8 : 4;
+  if (ranges_overlap(omega, n, rank, rank, U, rank, rank, es)) return fail(GP_ERR_ARG, "U overlaps omega");
+  const NysLayout L = nys_layout(k, n, rank);
+  if (!ws || ws_bytes < L.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                ws ? ws_bytes : (size_t)0);
+  if (k->prec == GP_F64)
+    return run_nystrom<double>(k, n, X, theta, rank, (const double *)omega, (double *)U, lam,
+                               (char *)ws, L, stream);
+  return run_nystrom<float>(k, n, X, theta, rank, (const float *)omega, (float *)U, lam, (char *)ws,
+                            L, stream);
+}
+
+size_t gp_pcg_workspace_size(const gp_kernel *k, int64_t n, int32_t r, int32_t rank) {
+  if (gp_n_theta(k) < 0 || (k->flags & GP_NO_NOISE) || n < 1 || r < 1 || r > kPcgMaxR || rank < 0 ||
+      rank > kRankMax)
+    return 0;
+  return pcg_layout(k, n, r, rank).total;
+}
+
+gp_status gp_pcg_solve(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                       int32_t r, const void *B, int64_t ldb, void *x, int64_t ldx,
+                       const double *col_shift, int32_t rank, const void *U, const double *lam,
+                       double tol, int32_t maxit, int32_t *status, int32_t *iters, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  if (gp_n_theta(k) < 0) return fail(GP_ERR_ARG, "invalid kernel description");
+  if (k->flags & GP_NO_NOISE) return fail(GP_ERR_ARG, "GP_NO_NOISE: K alone need not be invertible");
+  if (n < 1) return fail(GP_ERR_SHAPE, "n = %lld < 1", (long long)n);
+  if (r < 1 || r > kPcgMaxR) return fail(GP_ERR_SHAPE, "r = %d outside 1..%d", r, kPcgMaxR);
+  if (rank < 0 || rank > kRankMax) return fail(GP_ERR_SHAPE, "rank = %d outside 0..%d", rank, kRankMax);
+  if (!X || !theta || !B || !x) return fail(GP_ERR_ARG, "X, theta, B and x must be non-NULL");
+  if (rank > 0 && (!U || !lam)) return fail(GP_ERR_ARG, "rank > 0 needs U and lam");
+  if (ldb < r || ldx < r) return fail(GP_ERR_SHAPE, "leading dimensions must be >= r = %d", r);
+  if (!(tol > 0.0)) return fail(GP_ERR_ARG, "tol must be > 0");
+  if (maxit < 0) return fail(GP_ERR_ARG, "maxit must be >= 0");
+  const size_t es = k->prec == GP_F64 ? 8 : 4;
+  if (ranges_overlap(B, n, ldb, r, x, ldx, r, es)) return fail(GP_ERR_ARG, "x overlaps B");
+  const PcgLayout L = pcg_layout(k, n, r, rank);
+  if (!ws || ws_bytes < L.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                ws ? ws_bytes : (size_t)0);
+  if (k->prec == GP_F64)
+    return run_pcg<double>(k, n, X, theta, r, (const double *)B, ldb, (double *)x, ldx, col_shift,
+                           rank, (const double *)U, lam, tol, maxit, status, iters, (char *)ws, L,
+                           stream);
+  return run_pcg<float>(k, n, X, theta, r, (const float *)B, ldb, (float *)x, ldx, col_shift, rank,
+                        (const float *)U, lam, tol, maxit, status, iters, (char *)ws, L, stream);
+}
+
+}  // extern "C"

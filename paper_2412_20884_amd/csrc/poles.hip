@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "gpk.h"
+#include "vecops.h"
 
 namespace gpk {
 
@@ -42,7 +43,6 @@ namespace {
 
 constexpr int kPoleMax = 64;     // most poles per call
 constexpr int kPhiMaxR = 32;     // most right-hand sides per call
-constexpr int kVecBlocksMax = 2048;
 constexpr int kCheckEvery = 4;   // host convergence check period, iterations
 
 // ---- Jacobi elliptic functions by the AGM (host) ---------------------------------------------
@@ -117,38 +117,6 @@ struct PoleShift {    // one (right-hand side, pole) pair
   int32_t pad;
 };
 
-// Row tiling of the streaming kernels: thread t handles column t % r of rows t / r, t / r + rps,
-// ... with rps = 256 / r rows per sweep; a block covers `rows_per_block` consecutive rows.
-struct VecGrid {
-  int rps;
-  int64_t rows_per_block;
-  int64_t blocks;
-};
-
-VecGrid vec_grid(int64_t n, int r) {
-  VecGrid g;
-  g.rps = kThreads / r;
-  int64_t blocks = (n + g.rps - 1) / g.rps;
-  if (blocks > kVecBlocksMax) blocks = kVecBlocksMax;
-  int64_t rpb = (n + blocks - 1) / blocks;
-  rpb = ((rpb + g.rps - 1) / g.rps) * g.rps;
-  g.rows_per_block = rpb;
-  g.blocks = (n + rpb - 1) / rpb;
-  return g;
-}
-
-// Fixed-order per-column sum of the block's thread partials into part[blockIdx.x * r + c].
-__device__ void block_column_sum(double v, double *sh, int r, int rps, double *part) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  if (t < r) {
-    double s = 0.0;
-    for (int l = 0; l < rps; ++l) s += sh[l * r + t];
-    part[(int64_t)blockIdx.x * r + t] = s;
-  }
-}
-
 // r = p = xi, phi = 0, partial sums of xi . xi.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) phi_init(int64_t n, int r, VecGrid g, const T *xi,
@@ -185,22 +153,6 @@ __global__ void __launch_bounds__(kThreads) phi_dot(int64_t n, int r, VecGrid g,
       acc += (double)pv[i * r + c] * (double)qv[i * r + c];
   }
   block_column_sum(acc, sh, r, g.rps, part);
-}
-
-// Fixed-order sum of part[b * r + c] over the blocks, by all threads of the (single) block.
-__device__ double column_total(const double *part, int64_t blocks, int r, int c, double *red) {
-  const int t = threadIdx.x;
-  double s = 0.0;
-  for (int64_t b = t; b < blocks; b += blockDim.x) s += part[b * r + c];
-  red[t] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
-    if (t < w) red[t] += red[t + w];
-    __syncthreads();
-  }
-  const double tot = red[0];
-  __syncthreads();
-  return tot;
 }
 
 // Column and shift states before the first iteration.

@@ -20,12 +20,14 @@ NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
 CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED = 1, 2, 4, 8
 PHI_CG_MAXIT, PHI_NONFINITE = 1, 2
+CG_MAXIT, CG_NONFINITE = 1, 2
 
 EXPORTED = (
     "gp_last_error", "gp_status_string", "gp_n_theta", "gp_workspace_size", "gp_kmatvec",
     "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog", "gp_tune_workspace_size",
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
-    "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh",
+    "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
+    "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve",
 )
 
 
@@ -112,6 +114,15 @@ def lib():
     L.gp_phi_refresh.restype = _i32
     L.gp_phi_refresh.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams), _i64, _vp, _vp,
                                  _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gp_nystrom_workspace_size.restype = _sz
+    L.gp_nystrom_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32]
+    L.gp_nystrom.restype = _i32
+    L.gp_nystrom.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gp_pcg_workspace_size.restype = _sz
+    L.gp_pcg_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32, _i32]
+    L.gp_pcg_solve.restype = _i32
+    L.gp_pcg_solve.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp,
+                               _i32, _vp, _vp, ctypes.c_double, _i32, _vp, _vp, _vp, _sz, _vp]
     _LIB = L
     return L
 
@@ -373,3 +384,51 @@ def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit
                                 0 if w is None else w.numel(), _stream(dev)))
     return {"phi": out2[:, 0] if squeeze else out, "status": status, "iters": iters,
             "bounds": (bounds[0], bounds[1])}
+
+
+def nystrom(X, theta, omega, kind="iso", prec=None, n_cheb=0, ws=None):
+    """Randomized Nystrom factor K ~ U diag(lam) U^T for the n x rank test matrix omega.
+    Returns (U, lam)."""
+    _rowmajor(X, "X")
+    dev = X.device
+    _same(dev, X.dtype, omega=omega)
+    _same(dev, torch.float64, theta=theta)
+    if not omega.is_contiguous():
+        raise ValueError("omega must be contiguous")
+    k = make_kernel(kind, X, prec, n_cheb=n_cheb)
+    n, rank = omega.shape
+    U = torch.empty((n, rank), dtype=X.dtype, device=dev)
+    lam = torch.empty(rank, dtype=torch.float64, device=dev)
+    nbytes = int(lib().gp_nystrom_workspace_size(ctypes.byref(k), n, rank))
+    w = _workspace(nbytes, dev, ws)
+    _check(lib().gp_nystrom(ctypes.byref(k), n, _p(X), _p(theta), rank, _p(omega), _p(U), _p(lam),
+                            _p(w), 0 if w is None else w.numel(), _stream(dev)))
+    return U, lam
+
+
+def pcg_solve(X, theta, B, kind="iso", prec=None, x0=None, col_shift=None, U=None, lam=None,
+              tol=1e-6, maxit=5000, n_cheb=0, ws=None):
+    """(A + diag(col_shift)) x = B by (Nystrom-preconditioned if U is given) CG.  B may be 1-D.
+    Returns dict(x, status, iters)."""
+    squeeze = B.dim() == 1
+    B2 = B[:, None] if squeeze else B
+    _rowmajor(X, "X")
+    _rowmajor(B2, "B")
+    dev = X.device
+    _same(dev, X.dtype, B=B2, U=U)
+    _same(dev, torch.float64, theta=theta, col_shift=col_shift, lam=lam)
+    k = make_kernel(kind, X, prec, n_cheb=n_cheb)
+    n, r = B2.shape
+    rank = 0 if U is None else U.shape[1]
+    if U is not None and not U.is_contiguous():
+        raise ValueError("U must be contiguous")
+    x = torch.zeros((n, r), dtype=X.dtype, device=dev) if x0 is None else \
+        (x0[:, None] if x0.dim() == 1 else x0).clone().contiguous()
+    status = torch.empty(r, dtype=torch.int32, device=dev)
+    iters = torch.empty(r, dtype=torch.int32, device=dev)
+    nbytes = int(lib().gp_pcg_workspace_size(ctypes.byref(k), n, r, rank))
+    w = _workspace(nbytes, dev, ws)
+    _check(lib().gp_pcg_solve(ctypes.byref(k), n, _p(X), _p(theta), r, _p(B2), B2.stride(0), _p(x),
+                              x.stride(0), _p(col_shift), rank, _p(U), _p(lam), float(tol), int(maxit),
+                              _p(status), _p(iters), _p(w), 0 if w is None else w.numel(), _stream(dev)))
+    return {"x": x[:, 0] if squeeze else x, "status": status, "iters": iters}

@@ -138,3 +138,39 @@ def test_cheb_workspace_and_tuner():
     assert L.gp_workspace_size(ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 9)), 5000, 4) == 0
     assert L.gp_tune_workspace_size(k, 5000, 4) == 0
     assert L.gp_tune_products(k, 5000, 4, 1, None, 0, None) == 3
+
+
+def test_nystrom_and_pcg_validation():
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+    k = ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, 0))
+    nn = ctypes.byref(gpk.Kernel(gpk.ARD, gpk.F32, 4, gpk.NO_NOISE))
+
+    def ny(kk=k, n=100, rank=5, om=4096, U=1 << 20, lam=8, ws=8, wsb=1 << 40):
+        return L.gp_nystrom(kk, n, vp(1), vp(1), rank, vp(om), vp(U), vp(lam), vp(ws), wsb, None)
+
+    assert ny(rank=0) == 2
+    assert ny(rank=101) == 2
+    assert ny(rank=513, n=10000) == 2
+    assert ny(n=0) == 2
+    assert ny(lam=0) == 1
+    assert ny(U=4096 + 16) == 1        # U overlaps omega
+    assert ny(ws=0) == 4
+    assert L.gp_nystrom_workspace_size(k, 1000, 10) > 3 * 1000 * 10 * 4
+    assert L.gp_nystrom_workspace_size(k, 1000, 0) == 0
+
+    def pcg(kk=k, n=100, r=2, B=4096, ldb=2, x=1 << 20, ldx=2, rank=0, U=0, lam=0, tol=1e-6,
+            maxit=10, ws=8, wsb=1 << 40):
+        return L.gp_pcg_solve(kk, n, vp(1), vp(1), r, vp(B), ldb, vp(x), ldx, None, rank, vp(U),
+                              vp(lam), tol, maxit, None, None, vp(ws), wsb, None)
+
+    assert pcg(kk=nn) == 1
+    assert pcg(r=0) == 2
+    assert pcg(r=33) == 2
+    assert pcg(rank=3) == 1              # rank > 0 without U, lam
+    assert pcg(ldb=1) == 2
+    assert pcg(tol=0.0) == 1
+    assert pcg(x=4096 + 8) == 1          # x overlaps B
+    assert pcg(ws=0) == 4
+    assert L.gp_pcg_workspace_size(k, 1000, 4, 20) > L.gp_pcg_workspace_size(k, 1000, 4, 0)
+    assert L.gp_pcg_workspace_size(nn, 1000, 4, 0) == 0

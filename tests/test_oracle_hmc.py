@@ -153,3 +153,68 @@ def test_log_posterior_two_points_closed_form():
     quad = ((a + s2) * (y[0] ** 2 + y[1] ** 2) - 2 * off * y[0] * y[1]) / det
     expect = -0.5 * math.log(det) - 0.5 * quad
     assert abs(posterior.log_posterior(X, np.log([a, l, s2]), "iso", y) - expect) < 1e-13
+
+
+# ---- implicit midpoint (Section 3.2.3) ------------------------------------------------------
+
+
+def test_implicit_midpoint_is_the_cayley_map_on_a_quadratic_hamiltonian():
+    # H = 1/2 theta^T Q theta + 1/2 pi^T pi: the implicit midpoint map is the Cayley transform
+    # (I - dt/2 J H)^{-1} (I + dt/2 J H) of the linear flow, and it conserves H exactly
+    g = np.random.default_rng(5)
+    n = 4
+    B = g.standard_normal((n, n))
+    Q = B @ B.T + n * np.eye(n)
+    th0, pi0 = g.standard_normal(n), g.standard_normal(n)
+    dt = 0.3
+    th1, pi1 = hmc.implicit_midpoint_step(lambda m: Q @ m, th0, pi0, dt)
+    L = np.block([[np.zeros((n, n)), np.eye(n)], [-Q, np.zeros((n, n))]])   # d/dt (theta, pi)
+    I2 = np.eye(2 * n)
+    ref = np.linalg.solve(I2 - 0.5 * dt * L, (I2 + 0.5 * dt * L) @ np.concatenate([th0, pi0]))
+    np.testing.assert_allclose(np.concatenate([th1, pi1]), ref, rtol=1e-12, atol=1e-12)
+    H = lambda t, p: 0.5 * t @ Q @ t + 0.5 * p @ p
+    assert abs(H(th1, pi1) - H(th0, pi0)) < 1e-12 * H(th0, pi0)
+
+
+def _small_gp():
+    X = I.uniform_points(40, 2, 21)
+    y = I.y_sincos(X, 21)
+    th = I.theta_iso(1.0, 0.3, 0.05)
+    A = gp.a_matrix(X, th, "iso")
+    phi = np.linalg.solve(np.linalg.cholesky(A).T, I.rng(21, I.P_XI).standard_normal(40))
+    return X, y, th, phi
+
+
+def test_implicit_midpoint_gp_reversible_and_second_order():
+    X, y, th, phi = _small_gp()
+    pi0 = np.array([0.3, -0.5, 0.2])
+    th1, pi1 = hmc.implicit_midpoint(X, "iso", y, phi, th, pi0, 0.05, 3)
+    thb, pib = hmc.implicit_midpoint(X, "iso", y, phi, th1, -pi1, 0.05, 3)
+    np.testing.assert_allclose(thb, th, atol=1e-11)
+    np.testing.assert_allclose(-pib, pi0, atol=1e-10)
+    # the energy error of a symmetric second-order method falls by ~4 when dt halves
+    errs = []
+    for dt in (0.04, 0.02, 0.01):
+        t, p = hmc.implicit_midpoint(X, "iso", y, phi, th, pi0, dt, int(round(0.08 / dt)))
+        errs.append(abs(hmc.hamiltonian(X, t, "iso", y, phi, p) - hmc.hamiltonian(X, th, "iso", y, phi, pi0)))
+    assert 2.5 < errs[0] / errs[1] < 6.0 and 2.5 < errs[1] / errs[2] < 6.0, errs
+
+
+def test_implicit_midpoint_satisfies_its_defining_equations():
+    X, y, th, phi = _small_gp()
+    pi0 = np.array([0.1, 0.4, -0.3])
+    dt = 0.07
+    th1, pi1 = hmc.implicit_midpoint(X, "iso", y, phi, th, pi0, dt, 1)
+    m = 0.5 * (th + th1)
+    np.testing.assert_allclose(th1, th + dt * 0.5 * (pi0 + pi1), atol=1e-13)
+    # pi_1 = pi_0 - dt F(m), F by central differences of u(theta, x) at x = A(m)^{-1} y frozen
+    x = hmc.solve(X, m, "iso", y)
+    h = 1e-6
+    F = np.zeros(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        up = -0.5 * x @ gp.a_matrix(X, m + e, "iso") @ x + 0.5 * phi @ gp.a_matrix(X, m + e, "iso") @ phi
+        um = -0.5 * x @ gp.a_matrix(X, m - e, "iso") @ x + 0.5 * phi @ gp.a_matrix(X, m - e, "iso") @ phi
+        F[k] = (up - um) / (2 * h)
+    np.testing.assert_allclose(pi1, pi0 - dt * F, atol=1e-7)
