@@ -1,7 +1,7 @@
 """Benchmark of the hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-cpu] [--no-ard64]
-                    [--no-precond]
+                    [--no-precond] [--no-implicit]
 
 A step is one fused gp_quadform_grad pass over the large3 workload (N = 2^20 points uniform in
 [0,1]^3, isotropic SE kernel l = 0.05, alpha = 1, sigma^2 = 1e-3, 32 N(0,1) auxiliary vectors Z):
@@ -12,8 +12,9 @@ kernel), the FP64 oracle timed on a bounded row slab of the same workload on the
 a sampled parity check of the timed outputs, the batched-vs-plain HMC leapfrog comparison on the
 batched workload (64 instances, 8 chains each, 20-step trajectories) with phi drawn by the
 device Gibbs refresh (timed as its own leg), the d = 64 workload in the bfloat16 cross-term
-precision (product and force-pass rates, one short trajectory), and plain CG against
-Nystrom-preconditioned CG on the ard8 workload.
+precision (product and force-pass rates, one short trajectory), plain CG against
+Nystrom-preconditioned CG on the ard8 workload, and one implicit-midpoint trajectory (Anderson
+acceleration, Nystrom-based R) against the plain leapfrog trajectory of the same chain.
 """
 from __future__ import annotations
 
@@ -365,6 +366,57 @@ def bench_precond(rank=200):
     return out
 
 
+def bench_implicit(rank=50):
+    """One chain of the batched workload's first instance: a 20-step implicit-midpoint trajectory
+    (Anderson depth 10, Nystrom-based R of rank `rank`) against the plain-mode leapfrog
+    trajectory of the same chain, same dt and CG tolerance."""
+    import torch
+
+    from paper_2412_20884_amd import gpk, inputs
+
+    dev = "cuda:0"
+    wl = inputs.batched()
+    b = wl["instances"][0]
+    n, d = b["X"].shape
+    X = torch.tensor(b["X"], dtype=torch.float32, device=dev)
+    y = torch.tensor(b["y"], dtype=torch.float32, device=dev)
+    th0 = torch.tensor(b["theta"], dtype=torch.float64, device=dev)
+    phi = gpk.phi_refresh(X, th0, torch.tensor(b["xi"][0], dtype=torch.float32, device=dev), "ard",
+                          tol=1e-6, maxit=3000)["phi"].contiguous()
+    om = torch.tensor(inputs.normal_matrix(n, rank, 1000, inputs.P_V), dtype=torch.float32, device=dev)
+    out = {"workload": f"batched instance 0: N={n}, d={d}, ARD SE, sigma^2=0.1, FP32, one chain, "
+                       f"{wl['n_steps']} steps of dt {wl['dt']:g}; implicit: Anderson depth 10, Nystrom "
+                       f"rank {rank} for R, fixed-point tol 1e-4, linear tol 1e-6"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, lam = gpk.nystrom(X, th0, om, "ard")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    th, pi = th0.clone(), torch.tensor(b["pi"][0], dtype=torch.float64, device=dev)
+    x = torch.zeros(n, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    r = gpk.hmc_implicit(X, y, phi, th, pi, x, "ard", n_steps=wl["n_steps"], dt=wl["dt"], history=10,
+                         tol=1e-4, maxit=500, cg_tol=1e-6, U=U, lam=lam)
+    torch.cuda.synchronize()
+    t_imp = time.perf_counter() - t0
+    out["implicit"] = {"seconds": t_imp, "nystrom_build_seconds": t_build,
+                       "chain_steps_per_s": wl["n_steps"] / (t_imp + t_build),
+                       "fixed_point_iterations": int(r["iters"][0]), "status": int(r["status"][0]),
+                       "dH": float(r["H1"][0] - r["H0"][0])}
+    th, pi = th0.clone(), torch.tensor(b["pi"][0], dtype=torch.float64, device=dev)
+    x = torch.zeros(n, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi, th, pi, x, "ard", [n], [0], 1, d=[d],
+                         n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=1e-6, cg_maxit=3000, mode=gpk.PLAIN)
+    torch.cuda.synchronize()
+    t_lf = time.perf_counter() - t0
+    out["leapfrog_plain"] = {"seconds": t_lf, "chain_steps_per_s": wl["n_steps"] / t_lf,
+                             "cg_iterations": int(r["cg_iters"][0]), "status": int(r["status"][0]),
+                             "dH": float(r["H1"][0] - r["H0"][0])}
+    log(f"implicit: {out['implicit']}; leapfrog plain: {out['leapfrog_plain']}")
+    return out
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device copy of a known size, run under the same profiler command so its
     FETCH_SIZE / WRITE_SIZE readings calibrate the counters (bytes per counter unit)."""
@@ -393,6 +445,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ard64", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--no-implicit", action="store_true")
     ap.add_argument("--tune-load", default=None, help="load a saved tuning table instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -443,6 +496,8 @@ def main():
         line["ard64_bf16x"] = bench_ard64()
     if not args.no_precond:
         line["nystrom_precond"] = bench_precond()
+    if not args.no_implicit:
+        line["implicit_midpoint"] = bench_implicit()
     print(json.dumps(line), flush=True)
 
 

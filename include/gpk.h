@@ -81,7 +81,8 @@ enum {
   GP_CHAIN_CG_MAXIT = 1,        /* a linear solve hit cg_maxit before reaching cg_tol */
   GP_CHAIN_NONFINITE_H = 2,     /* an energy was NaN or infinite */
   GP_CHAIN_NONFINITE_THETA = 4, /* theta or pi became NaN or infinite */
-  GP_CHAIN_ABORTED = 8          /* the batched scheduler stopped before the chain finished */
+  GP_CHAIN_ABORTED = 8,         /* the batched scheduler stopped before the chain finished */
+  GP_CHAIN_FP_MAXIT = 16        /* an implicit step's fixed point was not reached in maxit */
 };
 
 /* Message of the last failed call on the calling thread ("" if none).  Valid until the next
@@ -329,6 +330,53 @@ gp_status gp_pcg_solve(const gp_kernel *k, int64_t n, const void *X, const doubl
                        const double *col_shift, int32_t rank, const void *U, const double *lam,
                        double tol, int32_t maxit, int32_t *status, int32_t *iters, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Implicit midpoint HMC (Section 3.2.3, eq. implicitsystem) solved by Anderson-accelerated
+ * fixed-point iteration of eq. (Phi) (Appendix B), for one chain.
+ *
+ * Each step seeks (theta_1, pi_1, x) with theta_1 = theta_0 + dt (pi_0 + pi_1)/2,
+ * pi_1 = pi_0 - dt F(m, x) and A(m) x = y at m = (theta_0 + theta_1)/2, as the fixed point of
+ * Phi(theta, pi, x) = (theta_0 + dt (pi_0 + pi)/2, pi_0 - dt F(m, x), x + (y - A(m) x)/c), where
+ * F is the frozen-x force of Section 3.2.1 and c ~ rho(A(theta_0)) from power iterations (the
+ * rescaling preconditioner R = I/c); with a Nystrom factor (rank > 0) R = P^{-1}/c instead, P
+ * the Nystrom preconditioner of A(theta_0) and c ~ rho(P^{-1} A(theta_0)) (the Nystrom-based R of
+ * Section 3.2.3).  Every evaluation of Phi is one fused quadratic-form pass
+ * over [x | phi].  The unknowns are stacked into one vector and accelerated with Anderson
+ * mixing of depth `history` (0: plain fixed-point iteration).  A step has converged when the
+ * (theta, pi) update is below tol (max norm, relative to 1 + |(theta, pi)|) and
+ * |y - A(m) x| <= cg_tol |y|.  The energies use solves at theta_0 and theta_1 by gp_pcg_solve
+ * (Nystrom-preconditioned when rank > 0) and the variational form of y^T A^{-1} y; the
+ * Metropolis decision is that of Algorithm 1.  The host drives the iteration; the call
+ * synchronises `stream`.
+ *   X, y, phi     device, n x d / n / n, kernel precision
+ *   theta, pi     device double[n_theta], in/out (accepted state or the start state); theta is
+ *                 also used as scratch during the call
+ *   x_warm        device, n: start of the first solve; on acceptance the solve at theta_1
+ *   u_accept      device double or NULL (no decision: the proposal is kept)
+ *   U, lam, rank  optional Nystrom factor (at theta_0) for R and the endpoint solves (rank 0: none)
+ *   H0, H1        device double; accepted, status (GP_CHAIN_* bits), iters (Anderson
+ *                 iterations over the trajectory) device int32
+ */
+typedef struct {
+  int32_t n_steps;   /* implicit steps per trajectory, N_int >= 0 */
+  double dt;         /* step size */
+  int32_t history;   /* Anderson depth k, 0..20 (10 in the paper) */
+  double tol;        /* fixed-point tolerance on (theta, pi), > 0 */
+  int32_t maxit;     /* fixed-point iterations per step, >= 1 */
+  double cg_tol;     /* relative residual of the linear part and of the endpoint solves */
+  int32_t cg_maxit;  /* iteration limit of the endpoint solves */
+  int32_t power_its; /* power iterations for c (10 in the paper), >= 1 */
+} gp_implicit_params;
+
+size_t gp_implicit_workspace_size(const gp_kernel *k, const gp_implicit_params *p, int64_t n,
+                                  int32_t rank);
+gp_status gp_hmc_implicit(const gp_kernel *k, const gp_implicit_params *p, int64_t n,
+                          const void *X, const void *y, const void *phi, double *theta, double *pi,
+                          void *x_warm, const double *u_accept, int32_t rank, const void *U,
+                          const double *lam, double *H0, double *H1, int32_t *accepted,
+                          int32_t *status, int32_t *iters, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@
 
 #include "common.h"
 #include "gpk.h"
+#include "nystrom.h"
 #include "vecops.h"
 
 namespace gpk {
@@ -551,7 +552,7 @@ __global__ void copy_block(int64_t n, int r, const T *a, T *b) {
 }
 
 struct PcgLayout {
-  size_t prod, prod_bytes, rv, zv, pv, qv, part, gpart, tkc, M, col, remaining, total;
+  size_t prod, prod_bytes, rv, zv, pv, qv, part, scr, col, remaining, total;
 };
 
 PcgLayout pcg_layout(const gp_kernel *k, int64_t n, int r, int rank) {
@@ -571,12 +572,8 @@ PcgLayout pcg_layout(const gp_kernel *k, int64_t n, int r, int rank) {
   o += align256(es * n * r);
   L.part = o;
   o += align256(sizeof(double) * kVecBlocksMax * r);
-  L.gpart = o;
-  o += align256(sizeof(double) * (size_t)gram_plan(n).nchunk * std::max(rank, 1) * r);
-  L.tkc = o;
-  o += align256(sizeof(double) * std::max(rank, 1) * r);
-  L.M = o;
-  o += align256(sizeof(double) * std::max(rank, 1) * r);
+  L.scr = o;
+  o += align256(nystrom_apply_scratch(n, std::max(rank, 1), r));
   L.col = o;
   o += align256(sizeof(PcgCol) * r);
   L.remaining = o;
@@ -604,13 +601,7 @@ gp_status run_pcg(const gp_kernel *k, int64_t n, const void *X, const double *th
       copy_block<T><<<eb, 256, 0, s>>>(n, r, rv, zv);
       e = hipGetLastError();
     } else {
-      double *tkc = (double *)(w + L.tkc), *M = (double *)(w + L.M);
-      e = gram<T>(n, rank, U, rank, r, rv, r, (double *)(w + L.gpart), tkc, s);
-      if (e == hipSuccess) {
-        pcg_prec_scale<<<(unsigned)((rank * r + 255) / 256), 256, 0, s>>>(rank, r, lam, theta, nth,
-                                                                          shift, tkc, M);
-        e = rmul<T>(n, rank, U, rank, M, r, rv, r, zv, r, s);
-      }
+      e = nystrom_apply<T>(n, rank, U, lam, theta, nth, shift, r, rv, zv, w + L.scr, s);
     }
     return e == hipSuccess ? GP_OK : hip_fail(e, "preconditioner");
   };
@@ -665,6 +656,33 @@ bool ranges_overlap(const void *a, int64_t rows, int64_t lda, int cols, const vo
 }
 
 }  // namespace
+
+size_t nystrom_apply_scratch(int64_t n, int rank, int r) {
+  return align256(sizeof(double) * (size_t)gram_plan(n).nchunk * rank * r) +
+         2 * align256(sizeof(double) * (size_t)rank * r);
+}
+
+template <typename T>
+hipError_t nystrom_apply(int64_t n, int rank, const T *U, const double *lam, const double *theta,
+                         int nth, const double *shift, int r, const T *v, T *z, char *scratch,
+                         hipStream_t s) {
+  double *gpart = (double *)scratch;
+  double *tkc = (double *)(scratch + align256(sizeof(double) * (size_t)gram_plan(n).nchunk * rank * r));
+  double *M = tkc + align256(sizeof(double) * (size_t)rank * r) / sizeof(double);
+  hipError_t e = gram<T>(n, rank, U, rank, r, v, r, gpart, tkc, s);
+  if (e != hipSuccess) return e;
+  pcg_prec_scale<<<(unsigned)((rank * r + 255) / 256), 256, 0, s>>>(rank, r, lam, theta, nth, shift,
+                                                                    tkc, M);
+  return rmul<T>(n, rank, U, rank, M, r, v, r, z, r, s);
+}
+
+template hipError_t nystrom_apply<float>(int64_t, int, const float *, const double *,
+                                         const double *, int, const double *, int, const float *,
+                                         float *, char *, hipStream_t);
+template hipError_t nystrom_apply<double>(int64_t, int, const double *, const double *,
+                                          const double *, int, const double *, int, const double *,
+                                          double *, char *, hipStream_t);
+
 }  // namespace gpk
 
 using namespace gpk;

@@ -18,7 +18,7 @@ ISO, ARD, CHEB = 0, 1, 2
 F64, F32, BF16X = 0, 1, 2
 NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
-CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED = 1, 2, 4, 8
+CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED, CHAIN_FP_MAXIT = 1, 2, 4, 8, 16
 PHI_CG_MAXIT, PHI_NONFINITE = 1, 2
 CG_MAXIT, CG_NONFINITE = 1, 2
 
@@ -27,7 +27,8 @@ EXPORTED = (
     "gp_quadform_grad", "gp_hmc_workspace_size", "gp_hmc_leapfrog", "gp_tune_workspace_size",
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
     "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
-    "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve",
+    "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve", "gp_implicit_workspace_size",
+    "gp_hmc_implicit",
 )
 
 
@@ -51,6 +52,12 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_inst", ctypes.c_int32), ("chains_per_inst", ctypes.c_int32),
                 ("n_points", ctypes.POINTER(ctypes.c_int64)), ("offsets", ctypes.POINTER(ctypes.c_int64)),
                 ("d", ctypes.POINTER(ctypes.c_int32)), ("x_offsets", ctypes.POINTER(ctypes.c_int64))]
+
+
+class ImplicitParams(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("dt", ctypes.c_double), ("history", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int32), ("power_its", ctypes.c_int32)]
 
 
 class PhiParams(ctypes.Structure):
@@ -123,6 +130,11 @@ def lib():
     L.gp_pcg_solve.restype = _i32
     L.gp_pcg_solve.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp,
                                _i32, _vp, _vp, ctypes.c_double, _i32, _vp, _vp, _vp, _sz, _vp]
+    L.gp_implicit_workspace_size.restype = _sz
+    L.gp_implicit_workspace_size.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(ImplicitParams), _i64, _i32]
+    L.gp_hmc_implicit.restype = _i32
+    L.gp_hmc_implicit.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(ImplicitParams), _i64, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     _LIB = L
     return L
 
@@ -180,7 +192,9 @@ def n_theta(kind, d, n_cheb=0):
 
 
 def _rowmajor(t, name):
-    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+    # strides of size-1 dimensions carry no meaning (torch may report any value for them)
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or \
+            (t.shape[0] > 1 and t.stride(0) < t.shape[1]):
         raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
 
 
@@ -432,3 +446,32 @@ def pcg_solve(X, theta, B, kind="iso", prec=None, x0=None, col_shift=None, U=Non
                               x.stride(0), _p(col_shift), rank, _p(U), _p(lam), float(tol), int(maxit),
                               _p(status), _p(iters), _p(w), 0 if w is None else w.numel(), _stream(dev)))
     return {"x": x[:, 0] if squeeze else x, "status": status, "iters": iters}
+
+
+def hmc_implicit(X, y, phi, theta, pi, x_warm, kind="iso", n_steps=3, dt=0.1, history=10, tol=1e-10,
+                 maxit=200, cg_tol=1e-6, cg_maxit=5000, power_its=10, u=None, U=None, lam=None,
+                 prec=None, n_cheb=0, ws=None):
+    """One implicit-midpoint HMC trajectory of one chain through gp_hmc_implicit.
+
+    theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, iters)."""
+    _rowmajor(X, "X")
+    dev = X.device
+    _same(dev, X.dtype, y=y, phi=phi, x_warm=x_warm, U=U)
+    _same(dev, torch.float64, theta=theta, pi=pi, u=u, lam=lam)
+    for name, t in (("y", y), ("phi", phi), ("theta", theta), ("pi", pi), ("x_warm", x_warm)):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    k = make_kernel(kind, X, prec, n_cheb=n_cheb)
+    prm = ImplicitParams(int(n_steps), float(dt), int(history), float(tol), int(maxit), float(cg_tol),
+                         int(cg_maxit), int(power_its))
+    n = X.shape[0]
+    rank = 0 if U is None else U.shape[1]
+    out = {key: torch.empty(1, dtype=torch.float64, device=dev) for key in ("H0", "H1")}
+    out.update({key: torch.empty(1, dtype=torch.int32, device=dev) for key in ("accepted", "status", "iters")})
+    nbytes = int(lib().gp_implicit_workspace_size(ctypes.byref(k), ctypes.byref(prm), n, rank))
+    w = _workspace(nbytes, dev, ws)
+    _check(lib().gp_hmc_implicit(ctypes.byref(k), ctypes.byref(prm), n, _p(X), _p(y), _p(phi), _p(theta),
+                                 _p(pi), _p(x_warm), _p(u), rank, _p(U), _p(lam), _p(out["H0"]),
+                                 _p(out["H1"]), _p(out["accepted"]), _p(out["status"]), _p(out["iters"]),
+                                 _p(w), 0 if w is None else w.numel(), _stream(dev)))
+    return out

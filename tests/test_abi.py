@@ -174,3 +174,32 @@ def test_nystrom_and_pcg_validation():
     assert pcg(ws=0) == 4
     assert L.gp_pcg_workspace_size(k, 1000, 4, 20) > L.gp_pcg_workspace_size(k, 1000, 4, 0)
     assert L.gp_pcg_workspace_size(nn, 1000, 4, 0) == 0
+
+
+def test_implicit_validation():
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+    k = ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F64, 2, 0))
+
+    def imp(kk=k, prm=None, n=100, rank=0, U=0, lam=0, ws=8, wsb=1 << 40, y=4096):
+        prm = prm or gpk.ImplicitParams(3, 0.1, 10, 1e-8, 100, 1e-6, 100, 10)
+        return L.gp_hmc_implicit(kk, ctypes.byref(prm), n, vp(1), vp(y), vp(8192), vp(16), vp(32),
+                                 vp(1 << 20), None, rank, vp(U), vp(lam), vp(64), vp(72), vp(80),
+                                 vp(84), None, vp(ws), wsb, None)
+
+    assert imp(kk=None) == 1
+    assert imp(kk=ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F64, 2, gpk.NO_NOISE))) == 1
+    for bad in (gpk.ImplicitParams(-1, 0.1, 10, 1e-8, 100, 1e-6, 100, 10),
+                gpk.ImplicitParams(3, 0.1, 21, 1e-8, 100, 1e-6, 100, 10),
+                gpk.ImplicitParams(3, 0.1, 10, 0.0, 100, 1e-6, 100, 10),
+                gpk.ImplicitParams(3, 0.1, 10, 1e-8, 0, 1e-6, 100, 10),
+                gpk.ImplicitParams(3, 0.1, 10, 1e-8, 100, 1e-6, 100, 0)):
+        assert imp(prm=bad) == 1
+    assert imp(n=0) == 2
+    assert imp(rank=5) == 1          # rank without U, lam
+    assert imp(y=0) == 1
+    assert imp(ws=0) == 4
+    prm = gpk.ImplicitParams(3, 0.1, 10, 1e-8, 100, 1e-6, 100, 10)
+    prm0 = gpk.ImplicitParams(3, 0.1, 0, 1e-8, 100, 1e-6, 100, 10)
+    assert L.gp_implicit_workspace_size(k, ctypes.byref(prm), 1000, 0) > \
+        L.gp_implicit_workspace_size(k, ctypes.byref(prm0), 1000, 0) + 2 * 9 * 1000 * 8 - 1024
