@@ -33,6 +33,11 @@ METRIC = "pair-evals/s for K_θV + ∇θ at N=2^20; HMC leapfrog steps/s batched
 FLOP_PER_PAIR = 143          # 4R + 3d + 6 with R = 32, d = 3 (isotropic, U = V)
 PEAK_F16_MFMA = 2.5e15       # dense fp16 matrix-core peak, FLOP/s
 PEAK_F32_VECTOR = 157.3e12   # fp32 vector peak, FLOP/s
+# VALU issue bound of the pair kernel (its ISA: 12 full-rate VALU instructions and one v_exp_f32 per
+# pair and lane; 4 cycles per full-rate wave instruction, 10.5 measured per v_exp_f32; 1024 SIMDs
+# at 2.4 GHz, 64 lanes per wave)
+VALU_INSTR_PER_PAIR, EXP_CYCLES = 12, 10.5
+VALU_BOUND_PAIRS = 1024 * 2.4e9 * 64 / (VALU_INSTR_PER_PAIR * 4 + EXP_CYCLES)
 
 
 def log(msg):
@@ -483,7 +488,9 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "pair_mfma<3,32,1> (fp16 hi/lo split, 3 products per contraction)",
                      "flop_per_pair": FLOP_PER_PAIR,
-                     "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR},
+                     "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR,
+                     "valu_issue_bound_pair_evals_per_s": VALU_BOUND_PAIRS,
+                     "frac_of_valu_issue_bound": pairs_per_s_kernel / VALU_BOUND_PAIRS},
         "parity": par,
         "autotune": b["tuned"],
     }

@@ -345,7 +345,7 @@ gp_status gp_pcg_solve(const gp_kernel *k, int64_t n, const void *X, const doubl
  * over [x | phi].  The unknowns are stacked into one vector and accelerated with Anderson
  * mixing of depth `history` (0: plain fixed-point iteration).  A step has converged when the
  * (theta, pi) update is below tol (max norm, relative to 1 + |(theta, pi)|) and
- * |y - A(m) x| <= cg_tol |y|.  The energies use solves at theta_0 and theta_1 by gp_pcg_solve
+ * |y - A(m) x| <= tol |y|.  The energies use solves at theta_0 and theta_1 by gp_pcg_solve
  * (Nystrom-preconditioned when rank > 0) and the variational form of y^T A^{-1} y; the
  * Metropolis decision is that of Algorithm 1.  The host drives the iteration; the call
  * synchronises `stream`.
@@ -362,9 +362,9 @@ typedef struct {
   int32_t n_steps;   /* implicit steps per trajectory, N_int >= 0 */
   double dt;         /* step size */
   int32_t history;   /* Anderson depth k, 0..20 (10 in the paper) */
-  double tol;        /* fixed-point tolerance on (theta, pi), > 0 */
+  double tol;        /* fixed-point tolerance on (theta, pi) and on the linear part, > 0 */
   int32_t maxit;     /* fixed-point iterations per step, >= 1 */
-  double cg_tol;     /* relative residual of the linear part and of the endpoint solves */
+  double cg_tol;     /* relative residual of the endpoint solves (energies at theta_0, theta_1) */
   int32_t cg_maxit;  /* iteration limit of the endpoint solves */
   int32_t power_its; /* power iterations for c (10 in the paper), >= 1 */
 } gp_implicit_params;

@@ -391,7 +391,7 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
       } else {
         fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, rb, x, inv_c, fx, gx);
       }
-      if (fmax <= p.tol * (1.0 + vmax) && res <= p.cg_tol * ynorm) {
+      if (fmax <= p.tol * (1.0 + vmax) && res <= p.tol * ynorm) {
         conv = true;
         // take the last map value: theta_1, pi_1 from g
         for (int kx = 0; kx < nth; ++kx) {
