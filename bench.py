@@ -34,10 +34,10 @@ FLOP_PER_PAIR = 143          # 4R + 3d + 6 with R = 32, d = 3 (isotropic, U = V)
 PEAK_F16_MFMA = 2.5e15       # dense fp16 matrix-core peak, FLOP/s
 PEAK_F32_VECTOR = 157.3e12   # fp32 vector peak, FLOP/s
 # VALU issue bound of the pair kernel (its ISA: 12 full-rate VALU instructions and one v_exp_f32 per
-# pair and lane; 4 cycles per full-rate wave instruction, 10.5 measured per v_exp_f32; 1024 SIMDs
-# at 2.4 GHz, 64 lanes per wave)
-VALU_INSTR_PER_PAIR, EXP_CYCLES = 12, 10.5
-VALU_BOUND_PAIRS = 1024 * 2.4e9 * 64 / (VALU_INSTR_PER_PAIR * 4 + EXP_CYCLES)
+# pair and lane; measured with paper_2412_20884_amd/probes/valu_rate.hip: 4.1 cycles per full-rate
+# wave instruction, 8.1 per v_exp_f32; 1024 SIMDs at 2.4 GHz, 64 lanes per wave)
+VALU_INSTR_PER_PAIR, VALU_CYCLES, EXP_CYCLES = 12, 4.1, 8.1
+VALU_BOUND_PAIRS = 1024 * 2.4e9 * 64 / (VALU_INSTR_PER_PAIR * VALU_CYCLES + EXP_CYCLES)
 
 
 def log(msg):

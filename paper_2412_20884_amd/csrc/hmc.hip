@@ -23,6 +23,8 @@ hipError_t hmc_tiles_f32(void *, int, int, hipStream_t);
 hipError_t hmc_tiles_f64(void *, int, int, hipStream_t);
 hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, hipStream_t);
 hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, hipStream_t);
+hipError_t hmc_gather_f32(void *, int, hipStream_t);
+hipError_t hmc_gather_f64(void *, int, hipStream_t);
 hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
                               int, hipStream_t);
 hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
@@ -51,6 +53,8 @@ size_t chain_bytes(int prec) { return prec == GP_F64 ? sizeof(HmcChain<double>) 
 // Chains whose jobs run through the product entry points (gp_kmatvec / gp_quadform_grad) rather
 // than the persistent tile kernels: the bfloat16 cross term and the Chebyshev-amplitude kernel.
 bool uses_ext(int prec, int kind) { return prec == GP_BF16X || kind == GP_SE_CHEB; }
+
+constexpr int kPlainCheck = 4;  // plain mode: jobs between host checks of a tile chain
 
 int plain_splits(int64_t n) {
   const int64_t rb = (n + kHmcTile - 1) / kHmcTile;
@@ -361,16 +365,21 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
       const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
       const size_t off_done = f64 ? offsetof(HmcChain<double>, done) : offsetof(HmcChain<float>, done);
       const int n_jobs = L.n_rb[c] * L.n_cs[c];
+      const bool ext = uses_ext(k->prec, k->kind);
+      // tile chains are checked every kPlainCheck jobs: on a finished chain the tiles and the
+      // epilogue do nothing, so a few surplus launches are harmless; ext chains read their job
       for (int64_t guard = 0;; ++guard) {
-        if (guard > (int64_t)prm.max_jobs + 2)
+        if (guard > (int64_t)prm.max_jobs + 2 + kPlainCheck)
           return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
-        int done = 0;
-        e = hipMemcpyAsync(&done, (char *)cp + off_done, sizeof(int), hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
-        if (done) break;
+        if (ext || guard % kPlainCheck == 0) {
+          int done = 0;
+          e = hipMemcpyAsync(&done, (char *)cp + off_done, sizeof(int), hipMemcpyDeviceToHost, stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(stream);
+          if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
+          if (done) break;
+        }
         const int dpc = inst[c / chains].dp;
-        if (uses_ext(k->prec, k->kind)) {
+        if (ext) {
           // the job runs as one call of the product entry points
           int job = 0;
           e = hipMemcpyAsync(&job, (char *)cp + off_job, sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -386,6 +395,10 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
           if (ps != GP_OK) return ps;
         } else {
           e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);
+          // with column splits the product is gathered by a multi-workgroup pass before the
+          // (single-workgroup) epilogue
+          if (e == hipSuccess && L.n_cs[c] > 1)
+            e = f64 ? hmc_gather_f64(cp, L.n_rb[c], stream) : hmc_gather_f32(cp, L.n_rb[c], stream);
         }
         if (e == hipSuccess)
           e = f64 ? hmc_epilogue_f64(cp, prm, stream) : hmc_epilogue_f32(cp, prm, stream);

@@ -4,6 +4,7 @@
 #define GPK_HMC_KICKOFF hmc_kickoff_f64
 #define GPK_HMC_TILES hmc_tiles_f64
 #define GPK_HMC_EPILOGUE hmc_epilogue_f64
+#define GPK_HMC_GATHER hmc_gather_f64
 #define GPK_HMC_PERSISTENT hmc_persistent_f64
 #define GPK_HMC_CHAIN_BYTES hmc_chain_bytes_f64
 #define GPK_HMC_RESET hmc_reset_f64
