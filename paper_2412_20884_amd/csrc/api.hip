@@ -171,7 +171,7 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
   const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.max_splits;
   const int64_t fb = pl.max_splits > 1 ? (n + kThreads - 1) / kThreads : 0;
   const size_t scr = pl.use_mfma == 2 ? xm_scratch_bytes(n, k->d)
-                     : pl.use_mfma    ? mfma_scratch_bytes()
+                     : pl.use_mfma    ? mfma_scratch_bytes(n, pl.dp)
                                       : 0;
   pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec, scr);
   return pl;

@@ -27,6 +27,7 @@ namespace gpk {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __fp16 f16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace mf {
 
@@ -39,6 +40,17 @@ constexpr int kStrideH = 40;      // halves per LDS row of the split tiles (80 b
 constexpr int kFold = 4;          // tiles (of 64 columns) between folds of the float partials
 constexpr int kScaleTop = 14;     // operands scaled below 2^14
 constexpr int kAmaxBlocks = 64;
+
+// A column tile as stage_tiles lays it out in global memory: 16-byte chunks of Y^T hi, Y^T lo
+// (one row of 32 slot-ordered halves per (half, column c)), then with the gradient Q hi and Q lo
+// (one row of RP halves per point), then the coordinates (XS floats per point).
+template <int RP, int XS, int GM>
+struct StageGeom {
+  static constexpr int kYC = NHALF * RP * 4;
+  static constexpr int kQC = GM ? TJ * RP / 8 : 0;
+  static constexpr int kXC = TJ * XS / 4;
+  static constexpr int kChunks = 2 * kYC + 2 * kQC + kXC;
+};
 
 union H8 {
   f16x8 v;
@@ -83,6 +95,7 @@ struct MArgs {
   int nth, nrec;
   const int *scl;  // [0] eK (from theta), [1] eY, [2] eP, [3] eQ
   float *amax;     // [3][kAmaxBlocks] partial max |.| of Y, P*w, Q
+  u32x4 *stage;    // column tiles laid out by stage_tiles
 };
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -138,6 +151,63 @@ __global__ void scales_final(MArgs a, int *scl) {
   }
 }
 
+// Split, scale and lay out the column side of every 64-column tile in the order of the pair
+// kernel's LDS tile (StageGeom): Y^T hi and lo with column jl of half hh in slot 8 gg + q
+// (gg = (jl mod 16) / 4, q = 4 (jl / 16) + jl mod 4), Q hi and lo, and the coordinates.
+// Columns past n get Y = Q = 0 and a far-away point, so their kernel values vanish.
+template <int RP, int XS, int GM>
+__global__ __launch_bounds__(256) void stage_tiles(MArgs a, int64_t ntiles) {
+  using G = StageGeom<RP, XS, GM>;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ntiles * G::kChunks) return;
+  const int64_t tile = e / G::kChunks;
+  int k = (int)(e - tile * G::kChunks);
+  const int64_t jt = tile * TJ;
+  union {
+    u32x4 v;
+    _Float16 h[8];
+    float f[4];
+  } out;
+  if (k < 2 * G::kYC) {
+    const bool lo = k >= G::kYC;
+    if (lo) k -= G::kYC;
+    const float sY = ldexpf(1.0f, a.scl[1]);
+    const int row = k >> 2, q = k & 3;  // row = hh RP + c; slots 8 q .. 8 q + 7
+    const int hh = row / RP, c = row - hh * RP;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int jl = 16 * (u >> 2) + 4 * q + (u & 3);
+      const int64_t j = jt + 32 * hh + jl;
+      float h, l;
+      split((j < a.n && c < a.R) ? a.Y[j * a.ldy + c] * sY : 0.0f, h, l);
+      out.h[u] = (_Float16)(lo ? l : h);
+    }
+  } else if (GM && k < 2 * G::kYC + 2 * G::kQC) {
+    k -= 2 * G::kYC;
+    const bool lo = k >= G::kQC;
+    if (lo) k -= G::kQC;
+    const float sQ = ldexpf(1.0f, a.scl[3]);
+    constexpr int kPerRow = RP / 8;
+    const int jj = k / kPerRow, c0 = 8 * (k - jj * kPerRow);
+    const int64_t j = jt + jj;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      float h, l;
+      split((j < a.n && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f, h, l);
+      out.h[u] = (_Float16)(lo ? l : h);
+    }
+  } else {
+    k -= 2 * G::kYC + 2 * G::kQC;
+    const int jj = (4 * k) / XS, k0 = 4 * k - jj * XS;
+    const int64_t j = jt + jj;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      out.f[u] = j < a.n ? a.xs[j * XS + k0 + u] : (k0 + u == 0 ? 1.0e18f : 0.0f);
+  }
+  a.stage[e] = out.v;
+}
+
 // GM: 0 product only, 1 isotropic gradient, 2 per-coordinate gradient.
 // D: coordinates used (1..4 stored with stride 4, or 8, 16).  RP: padded R (16 or 32).
 // IB: 16-row blocks per wave (1 or 2; the per-coordinate gradient at d >= 8 always uses 1,
@@ -149,7 +219,7 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   constexpr int NCB = RP / 16;               // 16-column blocks of the product
   constexpr int NG = GM == 2 ? D : 1;
   // LDS: double-buffered tile
-  __shared__ float sx[2][TJ * XS];
+  __shared__ __attribute__((aligned(16))) float sx[2][TJ * XS];
   __shared__ __attribute__((aligned(16))) _Float16 sqh[2][TJ * kStrideH];   // Q[j][c]
   __shared__ __attribute__((aligned(16))) _Float16 sql[2][TJ * kStrideH];
   __shared__ __attribute__((aligned(16))) _Float16 syh[2][NHALF * RP * kStrideH];  // Y^T[h][c][slot]
@@ -163,7 +233,6 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   const int R = a.R;
 
   const int eK = a.scl[0], eY = a.scl[1], eP = a.scl[2], eQ = a.scl[3];
-  const float sY = ldexpf(1.0f, eY), sQ = ldexpf(1.0f, eQ);
   const float c0 = (float)(a.theta[0] * kLog2e + (double)eK);
 
   // ---- row side: coordinates and the split weighted P operand (B of the S^T product) ----
@@ -223,72 +292,52 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   const int64_t j0 = (int64_t)blockIdx.y * a.col_chunk;
   const int64_t j1 = j0 + a.col_chunk < a.n ? j0 + a.col_chunk : a.n;
   const int ntiles = (int)((j1 - j0 + TJ - 1) / TJ);
-  const bool sym = (a.Y == a.Q && a.ldy == a.ldq);
-
-  // Column tiles (64 columns = two 32-column MFMA halves) are software-pipelined: the global
-  // loads of tile t + 2 are issued after the compute of tile t and land in registers; the
-  // registers of tile t + 1 are split and written to the other LDS buffer after the compute of
-  // tile t.  Out-of-range columns are zero in Y and Q and their coordinates are pushed far
-  // away so their kernel values vanish.
-  constexpr int NE = (TJ * RP + kWG - 1) / kWG;  // Y/Q elements per thread per tile
-  constexpr int NX = TJ * XS;                     // coordinate elements per tile
-  constexpr int NXT = (NX + kWG - 1) / kWG;
-  float ry[NE], rq[NE], rx[NXT];
-  // per-thread element positions are the same in every tile: offsets advance by TJ rows
-  int e_jj[NE], e_c[NE];
-  int64_t oy[NE], oq[NE];
+  // Column tiles (64 columns = two 32-column MFMA halves) are software-pipelined: tile t + 2 is
+  // loaded into registers after the compute of tile t, and tile t + 1 is written to the other
+  // LDS buffer.  Tiles arrive split and ordered from stage_tiles; every thread copies the same
+  // 16-byte chunk positions of every tile, so the destinations are fixed per thread.
+  using G = StageGeom<RP, XS, GM>;
+  constexpr int NCT = (G::kChunks + kWG - 1) / kWG;  // chunks per thread per tile
+  const u32x4 *stile = a.stage + (j0 / TJ) * G::kChunks;
+  u32x4 rv[NCT];
+  int dreg[NCT], doff[NCT];  // LDS region (0 Y hi, 1 Y lo, 2 Q hi, 3 Q lo, 4 coordinates), offset
 #pragma unroll
-  for (int u = 0; u < NE; ++u) {
-    const int e = tid + u * kWG;
-    e_jj[u] = e / RP;
-    e_c[u] = e - e_jj[u] * RP;
-    oy[u] = (j0 + e_jj[u]) * a.ldy + e_c[u];
-    oq[u] = (j0 + e_jj[u]) * a.ldq + e_c[u];
+  for (int u = 0; u < NCT; ++u) {
+    int k = tid + u * kWG;
+    if (k < 2 * G::kYC) {
+      dreg[u] = k >= G::kYC;
+      k -= dreg[u] * G::kYC;
+      doff[u] = (k >> 2) * kStrideH + 8 * (k & 3);
+    } else if (k < 2 * G::kYC + 2 * G::kQC) {
+      k -= 2 * G::kYC;
+      const int lo = k >= G::kQC;
+      dreg[u] = 2 + lo;
+      k -= lo * G::kQC;
+      constexpr int kPerRow = RP / 8;
+      doff[u] = (k / kPerRow) * kStrideH + 8 * (k % kPerRow);
+    } else {
+      dreg[u] = 4;
+      doff[u] = 4 * (k - 2 * G::kYC - 2 * G::kQC);
+    }
   }
-  const int64_t step_y = (int64_t)TJ * a.ldy, step_q = (int64_t)TJ * a.ldq;
   auto prefetch = [&](int t) {
-    const int64_t jt = j0 + (int64_t)t * TJ;
+    const u32x4 *src = stile + (int64_t)t * G::kChunks;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const bool ok = (tid + u * kWG) < TJ * RP && jt + e_jj[u] < j1 && e_c[u] < R;
-      ry[u] = ok ? a.Y[oy[u] + t * step_y] : 0.0f;
-      if (GM && !sym) rq[u] = ok ? a.Q[oq[u] + t * step_q] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < NXT; ++u) {
-      const int e = tid + u * kWG;
-      if (e < NX) {
-        const int jj = e / XS, k = e - jj * XS;
-        const int64_t j = jt + jj;
-        rx[u] = j < j1 ? a.xs[j * XS + k] : (k == 0 ? 1.0e18f : 0.0f);
-      }
-    }
+    for (int u = 0; u < NCT; ++u)
+      if (tid + u * kWG < G::kChunks) rv[u] = src[tid + u * kWG];
   };
   auto commit = [&](int b) {
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      if ((tid + u * kWG) < TJ * RP) {
-        const int jj = e_jj[u], c = e_c[u];
-        const int hh = jj >> 5, jl = jj & 31;
-        float h, l;
-        split(ry[u] * sY, h, l);
-        // slot of column jl of half hh in the transposed product operand
-        const int gg = (jl & 15) >> 2, q = 4 * (jl >> 4) + (jl & 3);
-        const int slot = 8 * gg + q;
-        syh[b][(hh * RP + c) * kStrideH + slot] = (_Float16)h;
-        syl[b][(hh * RP + c) * kStrideH + slot] = (_Float16)l;
-        if (GM) {
-          float qh, ql;
-          split((sym ? ry[u] : rq[u]) * sQ, qh, ql);
-          sqh[b][jj * kStrideH + c] = (_Float16)qh;
-          sql[b][jj * kStrideH + c] = (_Float16)ql;
+    for (int u = 0; u < NCT; ++u) {
+      if (tid + u * kWG < G::kChunks) {
+        switch (dreg[u]) {  // uniform per wave: region sizes are multiples of 64 chunks
+          case 0: *(u32x4 *)&syh[b][doff[u]] = rv[u]; break;
+          case 1: *(u32x4 *)&syl[b][doff[u]] = rv[u]; break;
+          case 2: *(u32x4 *)&sqh[b][doff[u]] = rv[u]; break;
+          case 3: *(u32x4 *)&sql[b][doff[u]] = rv[u]; break;
+          default: *(u32x4 *)&sx[b][doff[u]] = rv[u]; break;
         }
       }
-    }
-#pragma unroll
-    for (int u = 0; u < NXT; ++u) {
-      const int e = tid + u * kWG;
-      if (e < NX) sx[b][e] = rx[u];
     }
   };
   if (GM && RP < 32) {
@@ -561,6 +610,10 @@ __global__ __launch_bounds__(256) void finalise_mfma(MArgs a, int has_grad) {
 
 template <int D, int RP, int GM>
 static void launch_d_rp_gm(const MArgs &ma, int ib, dim3 grid, hipStream_t s) {
+  constexpr int XS = D <= 4 ? 4 : D;
+  const int64_t ntl = (ma.n + TJ - 1) / TJ;
+  const int64_t nch = ntl * StageGeom<RP, XS, GM>::kChunks;
+  stage_tiles<RP, XS, GM><<<(unsigned)((nch + 255) / 256), 256, 0, s>>>(ma, ntl);
   if constexpr (GM == 2 && D >= 8) {
     pair_mfma<D, RP, GM, 1><<<grid, kWG, 0, s>>>(ma);
   } else {
@@ -609,8 +662,16 @@ bool mfma_supported(int prec, int kind, int d, int R) {
   return prec == kF32 && d <= 16 && R >= 8 && R <= 32;
 }
 
-// Extra workspace of the matrix-core pass: partial maxima and the four scale exponents.
-size_t mfma_scratch_bytes() { return align256(sizeof(float) * 3 * mf::kAmaxBlocks + 64); }
+static size_t mfma_head_bytes() { return align256(sizeof(float) * 3 * mf::kAmaxBlocks + 64); }
+
+// Extra workspace of the matrix-core pass: partial maxima, the four scale exponents and the
+// staged column tiles (sized for R = 32 with the gradient operand).
+size_t mfma_scratch_bytes(int64_t n, int dp) {
+  const int64_t ntl = (n + mf::TJ - 1) / mf::TJ;
+  const size_t chunks = (size_t)2 * mf::NHALF * 32 * 4 + (size_t)2 * mf::TJ * 32 / 8 +
+                        (size_t)mf::TJ * dp / 4;
+  return mfma_head_bytes() + align256((size_t)ntl * chunks * 16);
+}
 
 hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
   using namespace mf;
@@ -635,7 +696,8 @@ hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
   a.out = (float *)p.out;
   a.ldo = p.ldo;
   a.splits = p.splits;
-  a.col_chunk = (p.n + p.splits - 1) / p.splits;
+  // column chunks of the split grid are whole tiles, so no tile straddles two splits
+  a.col_chunk = ((p.n + p.splits - 1) / p.splits + TJ - 1) / TJ * TJ;
   a.outp = p.outp;
   a.rec = p.rec_pair;
   a.nth = p.nth;
@@ -643,6 +705,7 @@ hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
   a.amax = (float *)p.mfma_scratch;
   int *scl = (int *)((char *)p.mfma_scratch + sizeof(float) * 3 * kAmaxBlocks);
   a.scl = scl;
+  a.stage = (u32x4 *)((char *)p.mfma_scratch + mfma_head_bytes());
   const int gm = p.P ? (p.kind == 0 ? 1 : 2) : 0;
   absmax_partial<<<dim3(kAmaxBlocks, 3), 256, 0, s>>>(a);
   scales_final<<<1, 64, 0, s>>>(a, scl);

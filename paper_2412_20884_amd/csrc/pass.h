@@ -64,7 +64,7 @@ hipError_t launch_pass(const PassDesc &p, hipStream_t s);
 hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s);
 
 bool mfma_supported(int prec, int kind, int d, int R);
-size_t mfma_scratch_bytes();
+size_t mfma_scratch_bytes(int64_t n, int dp);
 
 // typed entry points, defined per precision
 hipError_t launch_pass_f32(const PassDesc &p, hipStream_t s);
