@@ -359,7 +359,10 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     const int b = t & 1;
-#pragma unroll 1
+    // both halves unrolled (constant LDS offsets) except for the per-coordinate gradient,
+    // whose accumulators leave no registers for it
+    constexpr int kHalfUnroll = GM == 2 ? 1 : NHALF;
+#pragma unroll kHalfUnroll
     for (int hf = 0; hf < NHALF; ++hf) {
       // ---- S^T for both 16-column quarters of this half and all row blocks ---------------
       f32x4 s[IB][2];
@@ -393,19 +396,24 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
           for (int k = 0; k < D; ++k) xj[k] = p0[k];
 #pragma unroll
           for (int ib = 0; ib < IB; ++ib) {
+            // the product-only pass takes the exp2 argument c0 - rho straight from the FMA
+            // chain; the gradient passes need rho itself (folding c0 there would cancel
+            // badly against the rho = 0 diagonal pairs in sum W rho)
             float d2[GM == 2 ? D : 1];
-            float rho = 0.f;
+            float rho = 0.f, arg = c0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
               const float u = xi[ib][k] - xj[k];
               if (GM == 2) {
                 d2[k] = u * u;
                 rho += d2[k];
-              } else {
+              } else if (GM == 1) {
                 rho = fmaf(u, u, rho);
+              } else {
+                arg = fmaf(-u, u, arg);
               }
             }
-            const float kk = __builtin_amdgcn_exp2f(c0 - rho);
+            const float kk = __builtin_amdgcn_exp2f(GM ? c0 - rho : arg);
             if (GM) {
               const float W = kk * s[ib][jb][r];
               if (GM == 1) {
