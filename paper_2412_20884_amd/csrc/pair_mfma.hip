@@ -20,6 +20,10 @@
 //
 // The sum of W over pairs (the log alpha gradient) is not accumulated per pair: it equals
 // sum_ic w_c D_ic (K Y)_ic and is formed from the row results (D is the operand paired with Y).
+//
+// Column side: a pre-pass (stage_tiles) writes every 64-column tile once per call, split,
+// scaled and laid out byte for byte as the LDS tile; the pair kernel streams the next tile into
+// its second LDS buffer with direct global-to-LDS copies while it computes the current one.
 #include "pass.h"
 
 namespace gpk {
@@ -41,15 +45,21 @@ constexpr int kFold = 4;          // tiles (of 64 columns) between folds of the 
 constexpr int kScaleTop = 14;     // operands scaled below 2^14
 constexpr int kAmaxBlocks = 64;
 
-// A column tile as stage_tiles lays it out in global memory: 16-byte chunks of Y^T hi, Y^T lo
-// (one row of 32 slot-ordered halves per (half, column c)), then with the gradient Q hi and Q lo
-// (one row of RP halves per point), then the coordinates (XS floats per point).
+// A column tile as stage_tiles lays it out in global memory, byte for byte the image of one
+// LDS tile buffer: Y^T hi and Y^T lo (a padded row of 32 slot-ordered halves per (half, column
+// c)), then with the gradient Q hi and Q lo (a padded row of 32 halves per point, c >= RP zero),
+// then the coordinates (XS floats per point), rounded up to whole 1 KB wave copies.
 template <int RP, int XS, int GM>
-struct StageGeom {
-  static constexpr int kYC = NHALF * RP * 4;
-  static constexpr int kQC = GM ? TJ * RP / 8 : 0;
-  static constexpr int kXC = TJ * XS / 4;
-  static constexpr int kChunks = 2 * kYC + 2 * kQC + kXC;
+struct TileGeom {
+  static constexpr int kRowB = kStrideH * 2;
+  static constexpr int kYB = NHALF * RP * kRowB;
+  static constexpr int kQB = GM ? TJ * kRowB : 0;
+  static constexpr int kXB = TJ * XS * 4;
+  static constexpr int kOffYL = kYB;
+  static constexpr int kOffQH = 2 * kYB;
+  static constexpr int kOffQL = 2 * kYB + kQB;
+  static constexpr int kOffX = 2 * kYB + 2 * kQB;
+  static constexpr int kBytes = (kOffX + kXB + 1023) / 1024 * 1024;
 };
 
 union H8 {
@@ -152,54 +162,59 @@ __global__ void scales_final(MArgs a, int *scl) {
 }
 
 // Split, scale and lay out the column side of every 64-column tile in the order of the pair
-// kernel's LDS tile (StageGeom): Y^T hi and lo with column jl of half hh in slot 8 gg + q
+// kernel's LDS tile (TileGeom): Y^T hi and lo with column jl of half hh in slot 8 gg + q
 // (gg = (jl mod 16) / 4, q = 4 (jl / 16) + jl mod 4), Q hi and lo, and the coordinates.
 // Columns past n get Y = Q = 0 and a far-away point, so their kernel values vanish.
 template <int RP, int XS, int GM>
 __global__ __launch_bounds__(256) void stage_tiles(MArgs a, int64_t ntiles) {
-  using G = StageGeom<RP, XS, GM>;
+  using G = TileGeom<RP, XS, GM>;
+  constexpr int kCh = G::kBytes / 16;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= ntiles * G::kChunks) return;
-  const int64_t tile = e / G::kChunks;
-  int k = (int)(e - tile * G::kChunks);
+  if (e >= ntiles * kCh) return;
+  const int64_t tile = e / kCh;
+  const int off = 16 * (int)(e - tile * kCh);
   const int64_t jt = tile * TJ;
   union {
     u32x4 v;
     _Float16 h[8];
     float f[4];
   } out;
-  if (k < 2 * G::kYC) {
-    const bool lo = k >= G::kYC;
-    if (lo) k -= G::kYC;
-    const float sY = ldexpf(1.0f, a.scl[1]);
-    const int row = k >> 2, q = k & 3;  // row = hh RP + c; slots 8 q .. 8 q + 7
-    const int hh = row / RP, c = row - hh * RP;
+  out.v = u32x4{0u, 0u, 0u, 0u};
+  if (off < G::kOffQH) {
+    const bool lo = off >= G::kOffYL;
+    const int o = off - (lo ? G::kOffYL : 0);
+    const int row = o / G::kRowB, cb = o - row * G::kRowB;  // row = hh RP + c
+    if (cb < 64) {
+      const float sY = ldexpf(1.0f, a.scl[1]);
+      const int q = cb >> 4;  // slots 8 q .. 8 q + 7
+      const int hh = row / RP, c = row - hh * RP;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int jl = 16 * (u >> 2) + 4 * q + (u & 3);
-      const int64_t j = jt + 32 * hh + jl;
-      float h, l;
-      split((j < a.n && c < a.R) ? a.Y[j * a.ldy + c] * sY : 0.0f, h, l);
-      out.h[u] = (_Float16)(lo ? l : h);
+      for (int u = 0; u < 8; ++u) {
+        const int jl = 16 * (u >> 2) + 4 * q + (u & 3);
+        const int64_t j = jt + 32 * hh + jl;
+        float h, l;
+        split((j < a.n && c < a.R) ? a.Y[j * a.ldy + c] * sY : 0.0f, h, l);
+        out.h[u] = (_Float16)(lo ? l : h);
+      }
     }
-  } else if (GM && k < 2 * G::kYC + 2 * G::kQC) {
-    k -= 2 * G::kYC;
-    const bool lo = k >= G::kQC;
-    if (lo) k -= G::kQC;
-    const float sQ = ldexpf(1.0f, a.scl[3]);
-    constexpr int kPerRow = RP / 8;
-    const int jj = k / kPerRow, c0 = 8 * (k - jj * kPerRow);
-    const int64_t j = jt + jj;
+  } else if (off < G::kOffX) {
+    const bool lo = off >= G::kOffQL;
+    const int o = off - (lo ? G::kOffQL : G::kOffQH);
+    const int jj = o / G::kRowB, cb = o - jj * G::kRowB;
+    if (cb < 2 * RP) {
+      const float sQ = ldexpf(1.0f, a.scl[3]);
+      const int64_t j = jt + jj;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = c0 + u;
-      float h, l;
-      split((j < a.n && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f, h, l);
-      out.h[u] = (_Float16)(lo ? l : h);
+      for (int u = 0; u < 8; ++u) {
+        const int c = cb / 2 + u;
+        float h, l;
+        split((j < a.n && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f, h, l);
+        out.h[u] = (_Float16)(lo ? l : h);
+      }
     }
-  } else {
-    k -= 2 * G::kYC + 2 * G::kQC;
-    const int jj = (4 * k) / XS, k0 = 4 * k - jj * XS;
+  } else if (off < G::kOffX + G::kXB) {
+    const int f0 = (off - G::kOffX) / 4;
+    const int jj = f0 / XS, k0 = f0 - jj * XS;
     const int64_t j = jt + jj;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -219,11 +234,9 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   constexpr int NCB = RP / 16;               // 16-column blocks of the product
   constexpr int NG = GM == 2 ? D : 1;
   // LDS: double-buffered tile
-  __shared__ __attribute__((aligned(16))) float sx[2][TJ * XS];
-  __shared__ __attribute__((aligned(16))) _Float16 sqh[2][TJ * kStrideH];   // Q[j][c]
-  __shared__ __attribute__((aligned(16))) _Float16 sql[2][TJ * kStrideH];
-  __shared__ __attribute__((aligned(16))) _Float16 syh[2][NHALF * RP * kStrideH];  // Y^T[h][c][slot]
-  __shared__ __attribute__((aligned(16))) _Float16 syl[2][NHALF * RP * kStrideH];
+  using G = TileGeom<RP, XS, GM>;
+  __shared__ __attribute__((aligned(16))) char tile0[G::kBytes];
+  __shared__ __attribute__((aligned(16))) char tile1[G::kBytes];
   __shared__ double shr[kWaves][4];
 
   const int tid = threadIdx.x;
@@ -292,73 +305,30 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
   const int64_t j0 = (int64_t)blockIdx.y * a.col_chunk;
   const int64_t j1 = j0 + a.col_chunk < a.n ? j0 + a.col_chunk : a.n;
   const int ntiles = (int)((j1 - j0 + TJ - 1) / TJ);
-  // Column tiles (64 columns = two 32-column MFMA halves) are software-pipelined: tile t + 2 is
-  // loaded into registers after the compute of tile t, and tile t + 1 is written to the other
-  // LDS buffer.  Tiles arrive split and ordered from stage_tiles; every thread copies the same
-  // 16-byte chunk positions of every tile, so the destinations are fixed per thread.
-  using G = StageGeom<RP, XS, GM>;
-  constexpr int NCT = (G::kChunks + kWG - 1) / kWG;  // chunks per thread per tile
-  const u32x4 *stile = a.stage + (j0 / TJ) * G::kChunks;
-  u32x4 rv[NCT];
-  int dreg[NCT], doff[NCT];  // LDS region (0 Y hi, 1 Y lo, 2 Q hi, 3 Q lo, 4 coordinates), offset
+  // Column tiles (64 columns = two 32-column MFMA halves) are double-buffered: while tile t is
+  // computed from one LDS buffer, tile t + 1 streams into the other by direct global-to-LDS
+  // copies (each wave moves whole 1 KB blocks of the tile image stage_tiles wrote), and every
+  // wave waits for its copies before the barrier that ends the tile.
+  constexpr int kRounds = (G::kBytes / 1024 + kWaves - 1) / kWaves;
+  const char *gtiles = (const char *)a.stage + (j0 / TJ) * (int64_t)G::kBytes + lane * 16;
+  auto issue = [&](int t, char *dst) {
+    const char *src = gtiles + (int64_t)t * G::kBytes;
 #pragma unroll
-  for (int u = 0; u < NCT; ++u) {
-    int k = tid + u * kWG;
-    if (k < 2 * G::kYC) {
-      dreg[u] = k >= G::kYC;
-      k -= dreg[u] * G::kYC;
-      doff[u] = (k >> 2) * kStrideH + 8 * (k & 3);
-    } else if (k < 2 * G::kYC + 2 * G::kQC) {
-      k -= 2 * G::kYC;
-      const int lo = k >= G::kQC;
-      dreg[u] = 2 + lo;
-      k -= lo * G::kQC;
-      constexpr int kPerRow = RP / 8;
-      doff[u] = (k / kPerRow) * kStrideH + 8 * (k % kPerRow);
-    } else {
-      dreg[u] = 4;
-      doff[u] = 4 * (k - 2 * G::kYC - 2 * G::kQC);
-    }
-  }
-  auto prefetch = [&](int t) {
-    const u32x4 *src = stile + (int64_t)t * G::kChunks;
-#pragma unroll
-    for (int u = 0; u < NCT; ++u)
-      if (tid + u * kWG < G::kChunks) rv[u] = src[tid + u * kWG];
-  };
-  auto commit = [&](int b) {
-#pragma unroll
-    for (int u = 0; u < NCT; ++u) {
-      if (tid + u * kWG < G::kChunks) {
-        switch (dreg[u]) {  // uniform per wave: region sizes are multiples of 64 chunks
-          case 0: *(u32x4 *)&syh[b][doff[u]] = rv[u]; break;
-          case 1: *(u32x4 *)&syl[b][doff[u]] = rv[u]; break;
-          case 2: *(u32x4 *)&sqh[b][doff[u]] = rv[u]; break;
-          case 3: *(u32x4 *)&sql[b][doff[u]] = rv[u]; break;
-          default: *(u32x4 *)&sx[b][doff[u]] = rv[u]; break;
-        }
-      }
+    for (int u = 0; u < kRounds; ++u) {
+      const int off = (u * kWaves + wave) * 1024;
+      if (off < G::kBytes)
+        __builtin_amdgcn_global_load_lds(src + off,
+                                         (__attribute__((address_space(3))) void *)(dst + off),
+                                         16, 0, 0);
     }
   };
-  if (GM && RP < 32) {
-    // the unused half of the S contraction (c = RP .. 31) stays zero in both buffers
-    for (int e = tid; e < 2 * TJ * (32 - RP); e += kWG) {
-      const int bb = e / (TJ * (32 - RP));
-      const int r2 = e - bb * TJ * (32 - RP);
-      const int jj = r2 / (32 - RP), c = RP + (r2 - jj * (32 - RP));
-      sqh[bb][jj * kStrideH + c] = (_Float16)0.0f;
-      sql[bb][jj * kStrideH + c] = (_Float16)0.0f;
-    }
-  }
-
-  if (ntiles > 0) {
-    prefetch(0);
-    commit(0);
-  }
-  if (ntiles > 1) prefetch(1);
+  if (ntiles > 0) issue(0, tile0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int b = t & 1;
+  // two steps per loop trip, so that every LDS access names its buffer statically and the
+  // copies into one buffer do not hold up the reads of the other
+  auto tile_step = [&](int t, const char *cur, char *nxt) {
+    if (t + 1 < ntiles) issue(t + 1, nxt);
     // both halves unrolled (constant LDS offsets) except for the per-coordinate gradient,
     // whose accumulators leave no registers for it
     constexpr int kHalfUnroll = GM == 2 ? 1 : NHALF;
@@ -371,8 +341,8 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
         for (int jb = 0; jb < 2; ++jb) {
           H8 vh, vl;
           const int row = 32 * hf + 16 * jb + m;
-          vh.v = *(const f16x8 *)&sqh[b][row * kStrideH + 8 * g];
-          vl.v = *(const f16x8 *)&sql[b][row * kStrideH + 8 * g];
+          vh.v = *(const f16x8 *)(cur + G::kOffQH + 2 * (row * kStrideH + 8 * g));
+          vl.v = *(const f16x8 *)(cur + G::kOffQL + 2 * (row * kStrideH + 8 * g));
 #pragma unroll
           for (int ib = 0; ib < IB; ++ib) {
             f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -391,7 +361,7 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float xj[D];
-          const float *p0 = &sx[b][(32 * hf + 16 * jb + 4 * g + r) * XS];
+          const float *p0 = (const float *)(cur + G::kOffX) + (32 * hf + 16 * jb + 4 * g + r) * XS;
 #pragma unroll
           for (int k = 0; k < D; ++k) xj[k] = p0[k];
 #pragma unroll
@@ -442,8 +412,8 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         H8 yh, yl;
-        yh.v = *(const f16x8 *)&syh[b][(hf * RP + 16 * cb + m) * kStrideH + 8 * g];
-        yl.v = *(const f16x8 *)&syl[b][(hf * RP + 16 * cb + m) * kStrideH + 8 * g];
+        yh.v = *(const f16x8 *)(cur + 2 * ((hf * RP + 16 * cb + m) * kStrideH + 8 * g));
+        yl.v = *(const f16x8 *)(cur + G::kOffYL + 2 * ((hf * RP + 16 * cb + m) * kStrideH + 8 * g));
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           f32x4 z = acc[ib][cb];
@@ -454,8 +424,6 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
         }
       }
     }
-    if (t + 1 < ntiles) commit(b ^ 1);
-    if (t + 2 < ntiles) prefetch(t + 2);
     if ((t + 1) % kFold == 0 || t + 1 == ntiles) {
 #pragma unroll
       for (int ib = 0; ib < IB; ++ib)
@@ -477,7 +445,12 @@ __global__ __launch_bounds__(kWG) void pair_mfma(MArgs a) {
         }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of tile t + 1 have landed
     __syncthreads();
+  };
+  for (int t = 0; t < ntiles; t += 2) {
+    tile_step(t, tile0, tile1);
+    if (t + 1 < ntiles) tile_step(t + 1, tile1, tile0);
   }
 
   // ---- epilogue -----------------------------------------------------------------------------
@@ -620,7 +593,7 @@ template <int D, int RP, int GM>
 static void launch_d_rp_gm(const MArgs &ma, int ib, dim3 grid, hipStream_t s) {
   constexpr int XS = D <= 4 ? 4 : D;
   const int64_t ntl = (ma.n + TJ - 1) / TJ;
-  const int64_t nch = ntl * StageGeom<RP, XS, GM>::kChunks;
+  const int64_t nch = ntl * (TileGeom<RP, XS, GM>::kBytes / 16);
   stage_tiles<RP, XS, GM><<<(unsigned)((nch + 255) / 256), 256, 0, s>>>(ma, ntl);
   if constexpr (GM == 2 && D >= 8) {
     pair_mfma<D, RP, GM, 1><<<grid, kWG, 0, s>>>(ma);
@@ -676,9 +649,9 @@ static size_t mfma_head_bytes() { return align256(sizeof(float) * 3 * mf::kAmaxB
 // staged column tiles (sized for R = 32 with the gradient operand).
 size_t mfma_scratch_bytes(int64_t n, int dp) {
   const int64_t ntl = (n + mf::TJ - 1) / mf::TJ;
-  const size_t chunks = (size_t)2 * mf::NHALF * 32 * 4 + (size_t)2 * mf::TJ * 32 / 8 +
-                        (size_t)mf::TJ * dp / 4;
-  return mfma_head_bytes() + align256((size_t)ntl * chunks * 16);
+  const size_t tile = ((size_t)4 * mf::TJ * mf::kStrideH * 2 + (size_t)mf::TJ * dp * 4 + 1023) /
+                      1024 * 1024;
+  return mfma_head_bytes() + align256((size_t)ntl * tile);
 }
 
 hipError_t launch_pass_mfma(const PassDesc &p, hipStream_t s) {
