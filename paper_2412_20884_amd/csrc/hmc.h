@@ -67,12 +67,6 @@ struct HmcRunParams {
 };
 
 // Scheduling words of the batched launch, one per chain: (generation << 32) | claimed tiles.
-// Sizes of the kernel launches' static shared memory, shared by every tile variant.
-template <typename T>
-constexpr size_t hmc_tile_smem() {
-  return sizeof(T) * 64 * (kMaxD + 2) + 64;
-}
-
 struct HmcQueue {
   unsigned long long *word;
   unsigned int *finished;    // per chain: tiles finished in the current generation
