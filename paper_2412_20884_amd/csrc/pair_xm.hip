@@ -21,6 +21,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __fp16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace xm {
 
@@ -59,6 +60,32 @@ __device__ __forceinline__ void splitbf(float x, uint16_t &hb, uint16_t &lb) {
 }
 __device__ __forceinline__ float bfval(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// A 32-column tile as stage_tiles_xm lays it out in global memory, byte for byte the image of one
+// LDS tile buffer: bf16 coordinates hi and lo (a padded row of DPX values per point), the norms,
+// with the gradient Q hi and lo (a padded row of 32 halves per point, c >= RP zero), Y^T hi and lo
+// (a padded row of 32 slot-ordered halves per column c), and for the per-coordinate gradient the
+// bf16 hi and lo of [X | X^2 | 1]^T (a padded row of 32 slot-ordered values per k2), rounded up
+// to whole 1 KB wave copies.  Every region is a multiple of 16 bytes.
+template <int DPX, int RP, int GM>
+struct XTile {
+  static constexpr int XSTR = DPX + 8;
+  static constexpr int KB2 = GM == 2 ? (2 * DPX + 16) / 16 : 0;
+  static constexpr int kXB = TJ * XSTR * 2;
+  static constexpr int kNB = TJ * 4;
+  static constexpr int kQB = GM ? TJ * kStrideH * 2 : 0;
+  static constexpr int kYB = RP * kStrideH * 2;
+  static constexpr int kBB = KB2 * 16 * kStrideH * 2;
+  static constexpr int kOffXL = kXB;
+  static constexpr int kOffN = 2 * kXB;
+  static constexpr int kOffQH = kOffN + kNB;
+  static constexpr int kOffQL = kOffQH + kQB;
+  static constexpr int kOffYH = kOffQL + kQB;
+  static constexpr int kOffYL = kOffYH + kYB;
+  static constexpr int kOffBH = kOffYL + kYB;
+  static constexpr int kOffBL = kOffBH + kBB;
+  static constexpr int kBytes = (kOffBL + kBB + 1023) / 1024 * 1024;
+};
+
 struct XArgs {
   int64_t n;
   int R, L, d;
@@ -87,6 +114,7 @@ struct XArgs {
   int nth, nrec;
   const int *scl;
   float *amax;
+  u32x4 *stage;  // column tiles laid out by stage_tiles_xm
 };
 
 // hi/lo bf16 coordinates (zero-padded to dpx) and their compensated norms, one point per thread
@@ -158,6 +186,86 @@ __global__ void scales_final(XArgs a, int *scl) {
   }
 }
 
+// Split, scale and lay out the column side of every 32-column tile as the LDS image of XTile.
+// Columns past n get zero operands, a huge norm (their kernel values vanish) and no ones entry.
+template <int DPX, int RP, int GM>
+__global__ __launch_bounds__(256) void stage_tiles_xm(XArgs a, int64_t ntiles) {
+  using G = XTile<DPX, RP, GM>;
+  constexpr int kCh = G::kBytes / 16;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ntiles * kCh) return;
+  const int64_t tile = e / kCh;
+  const int off = 16 * (int)(e - tile * kCh);
+  const int64_t jt = tile * TJ;
+  union {
+    u32x4 v;
+    _Float16 h[8];
+    uint16_t u[8];
+    float f[4];
+  } out;
+  out.v = u32x4{0u, 0u, 0u, 0u};
+  // column of slot sl in the slot order of the products over j
+  auto slot_col = [](int sl) { return 16 * ((sl & 7) >> 2) + 4 * (sl >> 3) + (sl & 3); };
+  if (off < G::kOffN) {
+    const bool lo = off >= G::kOffXL;
+    const int o = off - (lo ? G::kOffXL : 0);
+    const int jj = o / (2 * G::XSTR), k0 = (o - jj * 2 * G::XSTR) / 2;
+    const int64_t j = jt + jj;
+    if (k0 < DPX && j < a.n) out.v = *(const u32x4 *)&(lo ? a.xl : a.xh)[j * DPX + k0];
+  } else if (off < G::kOffQH) {
+    const int jj0 = (off - G::kOffN) / 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out.f[u] = jt + jj0 + u < a.n ? a.nrm[jt + jj0 + u] : 1.0e30f;
+  } else if (off < G::kOffYH) {
+    const bool lo = off >= G::kOffQL;
+    const int o = off - (lo ? G::kOffQL : G::kOffQH);
+    const int jj = o / (2 * kStrideH), c0 = (o - jj * 2 * kStrideH) / 2;
+    const int64_t j = jt + jj;
+    const float sQ = ldexpf(1.0f, a.scl[3]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      float h, l;
+      split16((j < a.n && c < RP && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f, h, l);
+      out.h[u] = (_Float16)(lo ? l : h);
+    }
+  } else if (off < G::kOffBH) {
+    const bool lo = off >= G::kOffYL;
+    const int o = off - (lo ? G::kOffYL : G::kOffYH);
+    const int c = o / (2 * kStrideH), s0 = (o - c * 2 * kStrideH) / 2;
+    const float sY = ldexpf(1.0f, a.scl[1]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = s0 + u;
+      const int64_t j = jt + (sl < 32 ? slot_col(sl) : 0);
+      float h, l;
+      split16((sl < 32 && j < a.n && c < a.R) ? a.Y[j * a.ldy + c] * sY : 0.0f, h, l);
+      out.h[u] = (_Float16)(lo ? l : h);
+    }
+  } else if (GM == 2 && off < G::kOffBL + G::kBB) {
+    const bool lo = off >= G::kOffBL;
+    const int o = off - (lo ? G::kOffBL : G::kOffBH);
+    const int k2 = o / (2 * kStrideH), s0 = (o - k2 * 2 * kStrideH) / 2;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = s0 + u;
+      const int64_t j = jt + (sl < 32 ? slot_col(sl) : 0);
+      uint16_t hb = 0, lb = 0;
+      if (sl < 32 && j < a.n) {
+        if (k2 < 2 * DPX) {
+          const int k = k2 < DPX ? k2 : k2 - DPX;
+          const float x = k < a.xst ? a.xs[j * a.xst + k] : 0.0f;
+          splitbf(k2 < DPX ? x : x * x, hb, lb);
+        } else if (k2 == 2 * DPX) {
+          hb = 0x3F80;  // 1.0
+        }
+      }
+      out.u[u] = lo ? lb : hb;
+    }
+  }
+  a.stage[e] = out.v;
+}
+
 // DPX: padded coordinate width of the cross term (32 or 64).  RP: padded R (16 or 32).
 // GM: 0 product only, 1 isotropic gradient, 2 per-coordinate gradient.  IB: row blocks / wave.
 template <int DPX, int RP, int GM, int IB>
@@ -167,15 +275,9 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
   constexpr int KB2 = GM == 2 ? (2 * DPX + 16) / 16 : 1;  // blocks of [X | X^2 | 1]
   constexpr int XSTR = DPX + 8;              // halves per LDS row of the coordinate tile
   constexpr int kRowsWG = kWaves * IB * 16;
-  __shared__ __attribute__((aligned(16))) uint16_t sxh[2][TJ * XSTR];
-  __shared__ __attribute__((aligned(16))) uint16_t sxl[2][TJ * XSTR];
-  __shared__ float snrm[2][TJ];
-  __shared__ __attribute__((aligned(16))) _Float16 sqh[2][GM ? TJ * kStrideH : 8];
-  __shared__ __attribute__((aligned(16))) _Float16 sql[2][GM ? TJ * kStrideH : 8];
-  __shared__ __attribute__((aligned(16))) _Float16 syh[2][RP * kStrideH];
-  __shared__ __attribute__((aligned(16))) _Float16 syl[2][RP * kStrideH];
-  __shared__ __attribute__((aligned(16))) uint16_t sbh[2][GM == 2 ? KB2 * 16 * kStrideH : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t sbl[2][GM == 2 ? KB2 * 16 * kStrideH : 8];
+  using XT = XTile<DPX, RP, GM>;
+  __shared__ __attribute__((aligned(16))) char tile0[XT::kBytes];
+  __shared__ __attribute__((aligned(16))) char tile1[XT::kBytes];
   __shared__ double shr[kWaves];
   __shared__ double sred[kWaves][64];
 
@@ -185,7 +287,6 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * (IB * 16);
   const int R = a.R;
   const int eK = a.scl[0], eY = a.scl[1], eP = a.scl[2], eQ = a.scl[3];
-  const float sY = ldexpf(1.0f, eY), sQ = ldexpf(1.0f, eQ);
   const float c0 = (float)(a.theta[0] * kLog2e + (double)eK);
 
   // ---- row side ----------------------------------------------------------------------------
@@ -260,140 +361,39 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
   const int64_t j0 = (int64_t)blockIdx.y * a.col_chunk;
   const int64_t j1 = j0 + a.col_chunk < a.n ? j0 + a.col_chunk : a.n;
   const int ntiles = (int)((j1 - j0 + TJ - 1) / TJ);
-  const bool sym = (a.Y == a.Q && a.ldy == a.ldq);
 
-  // ---- column staging (register prefetch one tile ahead) -----------------------------------
-  constexpr int NE = (TJ * RP + kWG - 1) / kWG;
-  constexpr int NXW = TJ * DPX / 2;                 // uint32 words of one bf16 tile
-  constexpr int NXU = (NXW + kWG - 1) / kWG;
-  constexpr int NB2 = GM == 2 ? (TJ * DPX + kWG - 1) / kWG : 1;
-  float ry[NE], rq[NE], rn = 0.0f, rb[NB2];
-  uint32_t rxh[NXU], rxl[NXU];
-  auto prefetch = [&](int t) {
-    const int64_t jt = j0 + (int64_t)t * TJ;
+  // Column tiles are double-buffered: while tile t is computed from one LDS buffer, the waves
+  // copy tile t + 1 (the image stage_tiles_xm wrote) straight into the other in 1 KB blocks and
+  // wait for their copies only before the barrier that ends tile t.
+  constexpr int kRounds = (XT::kBytes / 1024 + kWaves - 1) / kWaves;
+  const char *gtiles = (const char *)a.stage + (j0 / TJ) * (int64_t)XT::kBytes + lane * 16;
+  auto issue = [&](int t, char *dst) {
+    const char *src = gtiles + (int64_t)t * XT::kBytes;
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kWG;
-      const int jj = e / RP, c = e - jj * RP;
-      const int64_t j = jt + jj;
-      const bool ok = e < TJ * RP && j < j1 && c < R;
-      ry[u] = ok ? a.Y[j * a.ldy + c] : 0.0f;
-      if (GM && !sym) rq[u] = ok ? a.Q[j * a.ldq + c] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < NXU; ++u) {
-      const int e = tid + u * kWG;  // word index within the tile
-      const int jj = e / (DPX / 2), kw = e - jj * (DPX / 2);
-      const int64_t j = jt + jj;
-      const bool ok = e < NXW && j < j1;
-      rxh[u] = ok ? ((const uint32_t *)a.xh)[j * (DPX / 2) + kw] : 0u;
-      rxl[u] = ok ? ((const uint32_t *)a.xl)[j * (DPX / 2) + kw] : 0u;
-    }
-    if (tid < TJ) {
-      const int64_t j = jt + tid;
-      // out-of-range columns get a huge norm so their kernel values vanish
-      rn = j < j1 ? a.nrm[j] : 1.0e30f;
-    }
-    if (GM == 2) {
-#pragma unroll
-      for (int u = 0; u < NB2; ++u) {
-        const int e = tid + u * kWG;
-        const int jj = e / DPX, k = e - jj * DPX;
-        const int64_t j = jt + jj;
-        rb[u] = (e < TJ * DPX && j < j1 && k < a.xst) ? a.xs[j * a.xst + k] : 0.0f;
-      }
+    for (int u = 0; u < kRounds; ++u) {
+      const int off = (u * kWaves + wave) * 1024;
+      if (off < XT::kBytes)
+        __builtin_amdgcn_global_load_lds(src + off,
+                                         (__attribute__((address_space(3))) void *)(dst + off),
+                                         16, 0, 0);
     }
   };
-  auto commit = [&](int b) {
-#pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kWG;
-      if (e < TJ * RP) {
-        const int jj = e / RP, c = e - jj * RP;
-        float h, l;
-        split16(ry[u] * sY, h, l);
-        const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
-        const int slot = 8 * gg + q;
-        syh[b][c * kStrideH + slot] = (_Float16)h;
-        syl[b][c * kStrideH + slot] = (_Float16)l;
-        if (GM) {
-          float qh, ql;
-          split16((sym ? ry[u] : rq[u]) * sQ, qh, ql);
-          sqh[b][jj * kStrideH + c] = (_Float16)qh;
-          sql[b][jj * kStrideH + c] = (_Float16)ql;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NXU; ++u) {
-      const int e = tid + u * kWG;
-      if (e < NXW) {
-        const int jj = e / (DPX / 2), kw = e - jj * (DPX / 2);
-        ((uint32_t *)sxh[b])[(jj * XSTR) / 2 + kw] = rxh[u];
-        ((uint32_t *)sxl[b])[(jj * XSTR) / 2 + kw] = rxl[u];
-      }
-    }
-    if (tid < TJ) snrm[b][tid] = rn;
-    if (GM == 2) {
-      // B operand of W [X | X^2 | 1], transposed to [k2][slot]
-#pragma unroll
-      for (int u = 0; u < NB2; ++u) {
-        const int e = tid + u * kWG;
-        if (e < TJ * DPX) {
-          const int jj = e / DPX, k = e - jj * DPX;
-          const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
-          const int slot = 8 * gg + q;
-          uint16_t hb, lb;
-          splitbf(rb[u], hb, lb);
-          sbh[b][k * kStrideH + slot] = hb;
-          sbl[b][k * kStrideH + slot] = lb;
-          splitbf(rb[u] * rb[u], hb, lb);
-          sbh[b][(DPX + k) * kStrideH + slot] = hb;
-          sbl[b][(DPX + k) * kStrideH + slot] = lb;
-        }
-      }
-    }
-  };
-  if (GM && RP < 32) {
-    // the unused half of the S contraction (c = RP .. 31) stays zero in both buffers
-    for (int e = tid; e < 2 * TJ * (32 - RP); e += kWG) {
-      const int bb = e / (TJ * (32 - RP));
-      const int r2 = e - bb * TJ * (32 - RP);
-      const int jj = r2 / (32 - RP), c = RP + (r2 - jj * (32 - RP));
-      sqh[bb][jj * kStrideH + c] = (_Float16)0.0f;
-      sql[bb][jj * kStrideH + c] = (_Float16)0.0f;
-    }
-  }
-  if (GM == 2) {
-    // the [1 | 0 ...] block (k2 = 2 DPX .. 2 DPX + 15) is constant: a ones row for valid
-    // columns is written per tile below; zero rows here
-    for (int e = tid; e < 2 * 16 * 32; e += kWG) {
-      const int bb = e / (16 * 32), rr = (e / 32) % 16, sl = e % 32;
-      sbh[bb][(2 * DPX + rr) * kStrideH + sl] = 0;
-      sbl[bb][(2 * DPX + rr) * kStrideH + sl] = 0;
-    }
-    __syncthreads();
-  }
-  auto commit_ones = [&](int b, int t) {
-    if (GM == 2 && tid < TJ) {
-      const int jj = tid;
-      const int gg = (jj & 15) >> 2, q = 4 * (jj >> 4) + (jj & 3);
-      const int slot = 8 * gg + q;
-      const bool ok = j0 + (int64_t)t * TJ + jj < j1;
-      sbh[b][(2 * DPX) * kStrideH + slot] = ok ? (uint16_t)0x3F80 : (uint16_t)0;  // 1.0
-      sbl[b][(2 * DPX) * kStrideH + slot] = 0;
-    }
-  };
-
-  if (ntiles > 0) {
-    prefetch(0);
-    commit(0);
-    commit_ones(0, 0);
-  }
-  if (ntiles > 1) prefetch(1);
+  if (ntiles > 0) issue(0, tile0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int b = t & 1;
+  // two tiles per loop trip, so that every LDS access names its buffer statically and the copies
+  // into one buffer do not hold up the reads of the other
+  auto tile_step = [&](int t, const char *cur, char *nxt) {
+    if (t + 1 < ntiles) issue(t + 1, nxt);
+    const uint16_t *sxh = (const uint16_t *)cur;
+    const uint16_t *sxl = (const uint16_t *)(cur + XT::kOffXL);
+    const float *snrm = (const float *)(cur + XT::kOffN);
+    const _Float16 *sqh = (const _Float16 *)(cur + XT::kOffQH);
+    const _Float16 *sql = (const _Float16 *)(cur + XT::kOffQL);
+    const _Float16 *syh = (const _Float16 *)(cur + XT::kOffYH);
+    const _Float16 *syl = (const _Float16 *)(cur + XT::kOffYL);
+    const uint16_t *sbh = (const uint16_t *)(cur + XT::kOffBH);
+    const uint16_t *sbl = (const uint16_t *)(cur + XT::kOffBL);
     // ---- cross term C^T[j][i] = x~_j . x~_i and quad weights S^T ---------------------------
     f32x4 C[IB][2], s[IB][2];
 #pragma unroll
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         B8 ah, al;
-        ah.v = *(const bf16x8 *)&sxh[b][(16 * jb + m) * XSTR + 32 * kc + 8 * g];
-        al.v = *(const bf16x8 *)&sxl[b][(16 * jb + m) * XSTR + 32 * kc + 8 * g];
+        ah.v = *(const bf16x8 *)&sxh[(16 * jb + m) * XSTR + 32 * kc + 8 * g];
+        al.v = *(const bf16x8 *)&sxl[(16 * jb + m) * XSTR + 32 * kc + 8 * g];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           f32x4 z = C[ib][jb];
@@ -416,8 +416,8 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
       }
       if (GM) {
         H8 vh, vl;
-        vh.v = *(const f16x8 *)&sqh[b][(16 * jb + m) * kStrideH + 8 * g];
-        vl.v = *(const f16x8 *)&sql[b][(16 * jb + m) * kStrideH + 8 * g];
+        vh.v = *(const f16x8 *)&sqh[(16 * jb + m) * kStrideH + 8 * g];
+        vl.v = *(const f16x8 *)&sql[(16 * jb + m) * kStrideH + 8 * g];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
       float kv[IB][4], wv[IB][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float nj = snrm[b][16 * jb + 4 * g + r];
+        const float nj = snrm[16 * jb + 4 * g + r];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           float tt = fmaf(2.0f, C[ib][jb][r], ai[ib] - nj);
@@ -480,8 +480,8 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       H8 yh, yl;
-      yh.v = *(const f16x8 *)&syh[b][(16 * cb + m) * kStrideH + 8 * g];
-      yl.v = *(const f16x8 *)&syl[b][(16 * cb + m) * kStrideH + 8 * g];
+      yh.v = *(const f16x8 *)&syh[(16 * cb + m) * kStrideH + 8 * g];
+      yl.v = *(const f16x8 *)&syl[(16 * cb + m) * kStrideH + 8 * g];
 #pragma unroll
       for (int ib = 0; ib < IB; ++ib) {
         f32x4 z = acc[ib][cb];
@@ -495,8 +495,8 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
 #pragma unroll
       for (int kb = 0; kb < KB2; ++kb) {
         B8 bh, bl;
-        bh.v = *(const bf16x8 *)&sbh[b][(16 * kb + m) * kStrideH + 8 * g];
-        bl.v = *(const bf16x8 *)&sbl[b][(16 * kb + m) * kStrideH + 8 * g];
+        bh.v = *(const bf16x8 *)&sbh[(16 * kb + m) * kStrideH + 8 * g];
+        bl.v = *(const bf16x8 *)&sbl[(16 * kb + m) * kStrideH + 8 * g];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           f32x4 z = wx[ib][kb];
@@ -507,11 +507,6 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
         }
       }
     }
-    if (t + 1 < ntiles) {
-      commit(b ^ 1);
-      commit_ones(b ^ 1, t + 1);
-    }
-    if (t + 2 < ntiles) prefetch(t + 2);
     if ((t + 1) % kFold == 0 || t + 1 == ntiles) {
 #pragma unroll
       for (int ib = 0; ib < IB; ++ib)
@@ -544,7 +539,12 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
         }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of tile t + 1 have landed
     __syncthreads();
+  };
+  for (int t = 0; t < ntiles; t += 2) {
+    tile_step(t, tile0, tile1);
+    if (t + 1 < ntiles) tile_step(t + 1, tile1, tile0);
   }
 
   // ---- epilogue -----------------------------------------------------------------------------
@@ -689,24 +689,40 @@ __global__ __launch_bounds__(256) void finalise_xm(XArgs a, int has_grad) {
   }
 }
 
+template <int DPX, int RP, int GM>
+static void stage_xm(const XArgs &xa, hipStream_t s) {
+  const int64_t ntl = (xa.n + TJ - 1) / TJ;
+  const int64_t nch = ntl * (XTile<DPX, RP, GM>::kBytes / 16);
+  stage_tiles_xm<DPX, RP, GM><<<(unsigned)((nch + 255) / 256), 256, 0, s>>>(xa, ntl);
+}
+
 template <int DPX, int RP>
 static void launch_dr(const XArgs &xa, int gm, dim3 grid, hipStream_t s) {
-  if (gm == 0)
+  if (gm == 0) {
+    stage_xm<DPX, RP, 0>(xa, s);
     pair_xm<DPX, RP, 0, 2><<<grid, kWG, 0, s>>>(xa);
-  else if (gm == 1)
+  } else if (gm == 1) {
+    stage_xm<DPX, RP, 1>(xa, s);
     pair_xm<DPX, RP, 1, 2><<<grid, kWG, 0, s>>>(xa);
-  else
+  } else {
+    stage_xm<DPX, RP, 2>(xa, s);
     pair_xm<DPX, RP, 2, 1><<<grid, kWG, 0, s>>>(xa);
+  }
 }
 
 }  // namespace xm
 
 int xm_rows_per_block(int has_grad_ard) { return xm::kWaves * 16 * (has_grad_ard ? 1 : 2); }
 int xm_dpx(int d) { return d <= 32 ? 32 : 64; }
+// staged tiles sized for the largest layout of the width: R = 32 with the per-coordinate gradient
+static size_t xm_stage_bytes(int64_t n, int dpx) {
+  const size_t tile = dpx == 32 ? xm::XTile<32, 32, 2>::kBytes : xm::XTile<64, 32, 2>::kBytes;
+  return align256((size_t)((n + xm::TJ - 1) / xm::TJ) * tile);
+}
 size_t xm_scratch_bytes(int64_t n, int d) {
   const int dpx = xm_dpx(d);
   return align256(sizeof(float) * 3 * xm::kAmaxBlocks + 64) + 2 * align256(2 * (size_t)n * dpx) +
-         align256(4 * (size_t)n);
+         align256(4 * (size_t)n) + xm_stage_bytes(n, dpx);
 }
 
 hipError_t launch_pass_xm(const PassDesc &p, hipStream_t s) {
@@ -721,6 +737,8 @@ hipError_t launch_pass_xm(const PassDesc &p, hipStream_t s) {
   uint16_t *xl = (uint16_t *)o;
   o += align256(2 * (size_t)p.n * dpx);
   float *nrm = (float *)o;
+  o += align256(4 * (size_t)p.n);
+  u32x4 *stage = (u32x4 *)o;
 
   XArgs a;
   a.n = p.n;
@@ -747,13 +765,15 @@ hipError_t launch_pass_xm(const PassDesc &p, hipStream_t s) {
   a.out = (float *)p.out;
   a.ldo = p.ldo;
   a.splits = p.splits;
-  a.col_chunk = (p.n + p.splits - 1) / p.splits;
+  // column chunks of the split grid are whole tiles, so no tile straddles two splits
+  a.col_chunk = ((p.n + p.splits - 1) / p.splits + TJ - 1) / TJ * TJ;
   a.outp = p.outp;
   a.rec = p.rec_pair;
   a.nth = p.nth;
   a.nrec = p.nrec;
   a.scl = scl;
   a.amax = amax;
+  a.stage = stage;
   const int gm = p.P ? (p.kind == 0 ? 1 : 2) : 0;
   xm_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>((const float *)p.xs, p.n, p.dp, dpx, xh,
                                                        xl, nrm);
