@@ -232,6 +232,32 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * gp_rwm -- one random-walk Metropolis update of theta given phi for every chain (the update of
+ * theta in Section 3 may be RWM or HMC; the proposal and acceptance rule are those given at the
+ * start of Section 4): the proposal
+ * theta' = theta + dt * xi, with xi ~ N(0, I) drawn by the caller, is accepted when
+ * log u <= U_phi(theta) - U_phi(theta').  Both energies U_phi (eq. U, without a kinetic term) come
+ * from one conjugate-gradient solve warm-started from x_warm and one quadratic-form pass each,
+ * exactly as the end-point energies of gp_hmc_leapfrog.  Parameters, batch packing, workspace
+ * (gp_hmc_workspace_size) and modes are those of gp_hmc_leapfrog; p->n_steps is ignored and
+ * p->dt is the proposal scale.
+ *
+ *   xi          device double per chain (packed as theta), in: the proposal direction; unchanged
+ *               on return
+ *   theta       device double, in/out: the accepted proposal, or the start state if rejected
+ *   x_warm      device, in/out: CG start at theta on entry; on return the solve at the returned
+ *               theta
+ *   u_accept    device double per chain, or NULL: no decision, every proposal is kept
+ *   U0, U1      device double per chain: U_phi at theta and at the proposal
+ *   accepted, status, cg_iters   as for gp_hmc_leapfrog
+ */
+gp_status gp_rwm(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, const void *X,
+                 const void *y, const void *phi, double *theta, double *xi, void *x_warm,
+                 const double *u_accept, double *U0, double *U1, int32_t *accepted,
+                 int32_t *status, int32_t *cg_iters, void *ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+/*
  * Gibbs refresh of phi (Section 3.1): given theta, phi | theta ~ N(0, A^{-1}) is drawn as
  * phi = A^{-1/2} xi with xi ~ N(0, I) supplied by the caller, through the pole expansion
  * A^{-1/2} ~ sum_p w_p (A + lambda_p I)^{-1} (eq. pex) with the weights and shifts of

@@ -16,6 +16,9 @@ Definitions followed (paper section / equation):
     (the printed kick has pi_1 on both sides; the reading used here starts from pi_0).
   * Metropolis test (Section 3.2, step (3); Algorithm 1): accept with probability
     min(1, exp(H_0 - H_1)); with a supplied uniform u the decision is  log u <= H_0 - H_1.
+  * Random-walk Metropolis (the RWM alternative for the update of theta in Section 3; proposal
+    and rule as stated at the start of Section 4): theta' = theta + dt * xi, xi ~ N(0, I),
+    accepted with probability min(1, exp(U_phi(theta) - U_phi(theta'))).
 
 The linear solve here is an exact Cholesky solve: the oracle never iterates.  The prior is
 flat (S = 0) unless a callable is supplied.
@@ -119,6 +122,24 @@ def trajectory(X, kind, y, phi, theta0, pi0, dt, n_steps, u=None, prior=None, gr
         "H1": H1,
         "accepted": ok,
     }
+
+
+def rwm_update(X, kind, y, phi, theta0, xi, dt, u=None, prior=None):
+    """One random-walk Metropolis update of theta given phi (the RWM alternative of Section 3,
+    with the proposal and acceptance rule stated at the start of Section 4): the proposal is
+    theta' = theta0 + dt * xi with xi ~ N(0, I) supplied, accepted with probability
+    min(1, exp(U_phi(theta0) - U_phi(theta'))); with a supplied uniform u the decision is
+    log u <= U_0 - U_1, and with u None the proposal is returned as accepted.
+
+    Returns dict(theta, theta_prop, U0, U1, accepted).
+    """
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    prop = theta0 + dt * np.asarray(xi, dtype=np.float64)
+    U0 = potential(X, theta0, kind, y, phi, prior)
+    U1 = potential(X, prop, kind, y, phi, prior)
+    ok = True if u is None else accept(U0, U1, u)
+    return {"theta": prop if ok else theta0.copy(), "theta_prop": prop, "U0": U0, "U1": U1,
+            "accepted": ok}
 
 
 # ---- implicit midpoint integrator (Section 3.2.3) ------------------------------------------

@@ -64,6 +64,7 @@ struct HmcRunParams {
   double tol2;  // cg_tol^2
   int cg_maxit;
   int max_jobs;  // (n_steps + 2) * (cg_maxit + 2) + 4: no trajectory can need more jobs
+  int rwm;       // 1: random-walk Metropolis update theta' = theta + dt * pi, no kinetic energy
 };
 
 // Scheduling words of the batched launch, one per chain: (generation << 32) | claimed tiles.

@@ -279,12 +279,12 @@ size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const g
   return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind, k->n_cheb).total;
 }
 
-gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
-                          const void *X, const void *y, const void *phi, double *theta,
-                          double *pi, void *x_warm, const double *u_accept, double *H0,
-                          double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
-                          void *ws, size_t ws_bytes, hipStream_t stream) {
-  clear_error();
+// One trajectory (rwm = 0) or one random-walk Metropolis update (rwm = 1) of every chain.
+static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
+                            const void *X, const void *y, const void *phi, double *theta,
+                            double *pi, void *x_warm, const double *u_accept, double *H0,
+                            double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
+                            void *ws, size_t ws_bytes, hipStream_t stream, int rwm) {
   std::vector<InstInfo> inst;
   gp_status st = collect(k, p, b, inst);
   if (st) return st;
@@ -341,12 +341,14 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   }
 
   HmcRunParams prm;
-  prm.n_steps = p->n_steps;
+  memset(&prm, 0, sizeof(prm));  // the bytes key the graph cache
+  prm.n_steps = rwm ? 0 : p->n_steps;
   prm.dt = p->dt;
   prm.tol2 = p->cg_tol * p->cg_tol;
   prm.cg_maxit = p->cg_maxit;
-  prm.max_jobs = (int)std::min<int64_t>((int64_t)(p->n_steps + 2) * (p->cg_maxit + 2) + 4,
+  prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (p->cg_maxit + 2) + 4,
                                         (int64_t)1 << 30);
+  prm.rwm = rwm;
   HmcQueue qu;
   qu.word = (unsigned long long *)(w + L.hdr_word);
   qu.finished = (unsigned *)(w + L.hdr_fin);
@@ -475,4 +477,24 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
   return GP_OK;
 }
 
+
+gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
+                          const void *X, const void *y, const void *phi, double *theta,
+                          double *pi, void *x_warm, const double *u_accept, double *H0,
+                          double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
+                          void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  return run_chains(k, p, b, X, y, phi, theta, pi, x_warm, u_accept, H0, H1, accepted, status,
+                    cg_iters, ws, ws_bytes, stream, 0);
+}
+
+gp_status gp_rwm(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, const void *X,
+                 const void *y, const void *phi, double *theta, double *xi, void *x_warm,
+                 const double *u_accept, double *U0, double *U1, int32_t *accepted,
+                 int32_t *status, int32_t *cg_iters, void *ws, size_t ws_bytes,
+                 hipStream_t stream) {
+  clear_error();
+  return run_chains(k, p, b, X, y, phi, theta, xi, x_warm, u_accept, U0, U1, accepted, status,
+                    cg_iters, ws, ws_bytes, stream, 1);
+}
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTED = (
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
     "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
     "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve", "gp_implicit_workspace_size",
-    "gp_hmc_implicit",
+    "gp_hmc_implicit", "gp_rwm",
 )
 
 
@@ -100,6 +100,10 @@ def lib():
                                         ctypes.POINTER(Batch)]
     L.gp_hmc_leapfrog.restype = _i32
     L.gp_hmc_leapfrog.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
+                                  ctypes.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gp_rwm.restype = _i32
+    L.gp_rwm.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
                                   ctypes.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     L.gp_tune_workspace_size.restype = _sz
@@ -323,6 +327,52 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
                                  _p(phi), _p(theta), _p(pi), _p(x_warm), _p(u), _p(H0), _p(H1),
                                  _p(acc), _p(st), _p(it), _p(ws), ws.numel(), _stream(dev)))
     return {"H0": H0, "H1": H1, "accepted": acc, "status": st, "cg_iters": it}
+
+
+def rwm(X, y, phi, theta, xi, x_warm, kind, n_points, offsets, chains, d=None, x_offsets=None,
+        u=None, dt=0.1, cg_tol=1e-6, cg_maxit=1000, mode=BATCHED, ws=None, cg_iters=True,
+        prec=None, n_cheb=0):
+    """One random-walk Metropolis update per chain through gp_rwm (packing as in include/gpk.h):
+    proposal theta + dt * xi, accepted when log u <= U0 - U1.
+
+    theta and x_warm are updated in place.  Returns dict(U0, U1, accepted, status, cg_iters).
+    """
+    dev = X.device
+    dt_ = X.dtype
+    _same(dev, dt_, y=y, phi=phi, x_warm=x_warm)
+    _same(dev, torch.float64, theta=theta, xi=xi, u=u)
+    for name, t in (("X", X), ("y", y), ("phi", phi), ("theta", theta), ("xi", xi), ("x_warm", x_warm)):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    n_inst = len(n_points)
+    dims = [X.shape[1]] * n_inst if d is None else list(d)
+    k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
+    prm = HmcParams(0, float(dt), float(cg_tol), int(cg_maxit), int(mode))
+    npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
+    offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
+    dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
+    xo = (ctypes.c_int64 * n_inst)(*[int(v) for v in x_offsets]) if x_offsets is not None else None
+    b = Batch(n_inst, int(chains), npts, offs, dd, xo)
+    nc = n_inst * chains
+    U0 = torch.empty(nc, dtype=torch.float64, device=dev)
+    U1 = torch.empty(nc, dtype=torch.float64, device=dev)
+    acc = torch.empty(nc, dtype=torch.int32, device=dev)
+    st = torch.empty(nc, dtype=torch.int32, device=dev)
+    it = torch.empty(nc, dtype=torch.int32, device=dev) if cg_iters else None
+    nbytes = hmc_workspace_size(k, prm, b)
+    if nbytes == 0:
+        _check(lib().gp_rwm(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, None, None,
+                            None, None, None, None, None, None, None, None, None, None, 0, None))
+    if ws is None:
+        key = (str(dev), nbytes)
+        ws = _HMC_WS.get(key)
+        if ws is None:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            _HMC_WS[key] = ws
+    _check(lib().gp_rwm(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), _p(X), _p(y), _p(phi),
+                        _p(theta), _p(xi), _p(x_warm), _p(u), _p(U0), _p(U1), _p(acc), _p(st),
+                        _p(it), _p(ws), ws.numel(), _stream(dev)))
+    return {"U0": U0, "U1": U1, "accepted": acc, "status": st, "cg_iters": it}
 
 
 def tune(kind, d, n, r, dtype=torch.float32, with_grad=True, device="cuda:0", prec=None):

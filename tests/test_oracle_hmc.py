@@ -218,3 +218,53 @@ def test_implicit_midpoint_satisfies_its_defining_equations():
         um = -0.5 * x @ gp.a_matrix(X, m - e, "iso") @ x + 0.5 * phi @ gp.a_matrix(X, m - e, "iso") @ phi
         F[k] = (up - um) / (2 * h)
     np.testing.assert_allclose(pi1, pi0 - dt * F, atol=1e-7)
+
+
+# ---- random-walk Metropolis (the RWM update of theta) ---------------------------------------
+
+
+def _one_point_potential(th, y, phi):
+    # N = 1: A = alpha + sigma^2 whatever the length-scale, so
+    # U = 1/2 y^2 / (alpha + sigma^2) + 1/2 phi^2 (alpha + sigma^2)
+    a = math.exp(th[0]) + math.exp(th[2])
+    return 0.5 * y * y / a + 0.5 * phi * phi * a
+
+
+def test_rwm_energies_and_proposal_one_point_closed_form():
+    X = np.array([[0.3]])
+    y, phi = 0.7, -1.3
+    th0 = np.array([0.2, -0.4, math.log(0.3)])
+    xi = np.array([0.5, 2.0, -1.5])
+    r = hmc.rwm_update(X, "iso", np.array([y]), np.array([phi]), th0, xi, 0.3)
+    prop = th0 + 0.3 * xi
+    assert abs(r["U0"] - _one_point_potential(th0, y, phi)) < 1e-13
+    assert abs(r["U1"] - _one_point_potential(prop, y, phi)) < 1e-13
+    np.testing.assert_allclose(r["theta"], prop, rtol=0, atol=1e-15)
+    assert r["accepted"]
+
+
+def test_rwm_acceptance_frequency_is_min_one_exp_energy_drop():
+    # over a fine grid of uniforms the accepted fraction is min(1, exp(U0 - U1)): exp of the
+    # energy drop when the proposal goes uphill, 1 when it goes downhill
+    X = np.array([[0.3]])
+    y, phi = 1.1, 0.4
+    th0 = np.array([0.0, 0.0, math.log(0.5)])
+    K = 20000
+    us = (np.arange(K) + 0.5) / K
+    for xi in (np.array([1.0, 0.0, 0.0]), np.array([-1.0, 0.0, -1.0]), np.array([0.3, 0.0, 0.8])):
+        u0 = _one_point_potential(th0, y, phi)
+        u1 = _one_point_potential(th0 + 0.5 * xi, y, phi)
+        frac = np.mean([hmc.rwm_update(X, "iso", np.array([y]), np.array([phi]), th0, xi, 0.5, u=u)["accepted"]
+                        for u in us[::20]])
+        assert abs(frac - min(1.0, math.exp(u0 - u1))) < 2e-3, (xi, frac, u0, u1)
+
+
+def test_rwm_reject_restores_and_zero_step_always_accepts():
+    X, y, th, phi = _problem()
+    xi = np.array([2.0, -1.0, 0.5])
+    r = hmc.rwm_update(X, "iso", y, phi, th, xi, 0.0, u=1.0 - 1e-15)
+    assert r["accepted"] and r["U0"] == r["U1"]
+    r = hmc.rwm_update(X, "iso", y, phi, th, xi, 0.4, u=1.0 - 1e-15)
+    if r["U1"] > r["U0"]:
+        assert not r["accepted"]
+        np.testing.assert_array_equal(r["theta"], th)
