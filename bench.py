@@ -268,6 +268,35 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
         torch.cuda.empty_cache()
     if "graph" in out and "plain" in out:
         out["speedup_batched_vs_plain"] = out["graph"]["chain_steps_per_s"] / out["plain"]["chain_steps_per_s"]
+    # random-walk Metropolis on the same chains: 20 graph-mode updates, proposal scale 0.05,
+    # xi ~ N(0, I) and u ~ U(0, 1) drawn here (seeded), the solve carried as the warm start
+    n_upd, scale = 20, 0.05
+    g = np.random.default_rng(20240)
+    th = torch.tensor(th0, dtype=torch.float64, device=dev)
+    x = torch.zeros(sum(ns) * C, dtype=torch.float32, device=dev)
+    xis = torch.tensor(g.normal(size=(n_upd, th.numel())), dtype=torch.float64, device=dev)
+    us = torch.tensor(g.uniform(size=(n_upd, len(ns) * C)), dtype=torch.float64, device=dev)
+    xi = torch.empty_like(th)
+    uu = torch.empty(len(ns) * C, dtype=torch.float64, device=dev)
+    acc_n, its_n, flagged = 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_upd):
+        xi.copy_(xis[k])
+        uu.copy_(us[k])
+        r = gpk.rwm(X, y, phi, th, xi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=uu, dt=scale,
+                    cg_tol=1e-6, cg_maxit=2000, mode=gpk.GRAPH)
+        acc_n += r["accepted"].sum()
+        its_n += r["cg_iters"].sum()
+        flagged += (r["status"] != 0).sum()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nchain = len(ns) * C
+    out["rwm_graph"] = {"chain_updates_per_s": nchain * n_upd / t, "seconds": t, "updates": n_upd,
+                        "proposal_scale": scale, "accept_rate": float(acc_n.item()) / (nchain * n_upd),
+                        "mean_cg_iters_per_update": float(its_n.item()) / (nchain * n_upd),
+                        "flagged_chains": int(flagged.item())}
+    log(f"rwm graph: {out['rwm_graph']}")
     out["phi_refresh"] = refresh
     out["workload"] = (f"batched: instances 0,{subset},{2 * subset},.. ({len(inst)} of 64; N_b in [2048, 32768], "
                        f"d_b in {{4,8,16}}), ARD SE, sigma^2=0.1, 8 chains each, {wl['n_steps']} leapfrog "
