@@ -72,7 +72,7 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def bench_large3(steps, warmup, tune=True, tune_load=None):
+def bench_large3(steps, warmup, tune=True, tune_load=None, tune_save=None):
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
@@ -88,11 +88,10 @@ def bench_large3(steps, warmup, tune=True, tune_load=None):
     elif tune:
         t0 = time.perf_counter()
         gpk.tune("iso", 3, n, r, torch.float32, with_grad=True)
-        path = os.path.join(ROOT, "gpurun_out", "tune_large3.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
         tuned = {"seconds": time.perf_counter() - t0}
-        if path:
-            gpk.tune_save(path)
-            tuned["table"] = path
+        if tune_save:
+            gpk.tune_save(tune_save)
+            tuned["table"] = tune_save
         log(f"tuned in {tuned['seconds']:.1f} s")
     X = torch.tensor(w["X"], dtype=torch.float32, device=dev)
     Z = torch.tensor(w["Z"], dtype=torch.float32, device=dev)
@@ -481,6 +480,7 @@ def main():
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-implicit", action="store_true")
     ap.add_argument("--tune-load", default=None, help="load a saved tuning table instead of tuning")
+    ap.add_argument("--tune-save", default=None, help="write the tuning table found here to this path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
@@ -495,7 +495,8 @@ def main():
     if args.copy_calibration:
         log(f"copy calibration: {copy_calibration()}")
     log("large3: generating inputs and warming up")
-    b = bench_large3(args.steps, args.warmup, tune=not args.no_tune, tune_load=args.tune_load)
+    b = bench_large3(args.steps, args.warmup, tune=not args.no_tune, tune_load=args.tune_load,
+                     tune_save=args.tune_save)
     n = b["n"]
     t_step = float(np.median(b["per_call"]))
     value = n * n * args.steps / b["wall"]
