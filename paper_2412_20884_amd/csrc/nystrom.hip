@@ -76,6 +76,57 @@ __global__ __launch_bounds__(256) void gram_partial(int64_t n, int l1, const T *
       if (j0 + jj + q < l2) out[(int64_t)(i0 + ii) * l2 + j0 + jj + q] = acc[q];
 }
 
+// The same partials for l2 <= L2P <= 32 columns of B (the preconditioner's U^T v): one thread per
+// row i of A^T streams its column of A (coalesced across threads), the chunk's rows of B are
+// staged in LDS 64 at a time; many small chunks keep the grid wide at any n.
+template <typename T, int L2P>
+__global__ __launch_bounds__(256) void gram_skinny(int64_t n, int l1, const T *A, int64_t lda,
+                                                   int l2, const T *B, int64_t ldb,
+                                                   int64_t rows_per_chunk, double *part) {
+  __shared__ double sb[64][L2P];
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(n, r0 + rows_per_chunk);
+  double acc[L2P];
+#pragma unroll
+  for (int j = 0; j < L2P; ++j) acc[j] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += 64) {
+    const int nr = (int)min((int64_t)64, r1 - rb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * L2P; e += 256) {
+      const int rr = e / L2P, c = e % L2P;
+      sb[rr][c] = (rr < nr && c < l2) ? (double)B[(rb + rr) * ldb + c] : 0.0;
+    }
+    __syncthreads();
+    if (i < l1) {
+      const T *a = A + rb * lda + i;
+      for (int rr = 0; rr < nr; ++rr) {
+        const double av = (double)a[rr * lda];
+#pragma unroll
+        for (int j = 0; j < L2P; ++j) acc[j] += av * sb[rr][j];
+      }
+    }
+  }
+  if (i < l1) {
+    double *out = part + ((int64_t)blockIdx.x * l1 + i) * l2;
+#pragma unroll
+    for (int j = 0; j < L2P; ++j)
+      if (j < l2) out[j] = acc[j];
+  }
+}
+
+// G[e] = sum over chunks of part[chunk][e], one wave per output (lanes over chunks, fixed order).
+__global__ __launch_bounds__(256) void gram_final_wave(int nchunk, int64_t m, const double *part,
+                                                       double *G) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double v = 0.0;
+  if (e < m)
+    for (int c = lane; c < nchunk; c += 64) v += part[(int64_t)c * m + e];
+  v = wave_sum(v);
+  if (e < m && lane == 0) G[e] = v;
+}
+
 __global__ void gram_final(int nchunk, int64_t m, const double *part, double *G) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= m) return;
@@ -246,9 +297,44 @@ Gram gram_plan(int64_t n) {
   return g;
 }
 
+// Chunks of the skinny Gram (l2 <= 32): about 512 rows each, at most ~2^20 partial doubles.
+Gram skinny_plan(int64_t n, int l1, int l2) {
+  Gram g;
+  const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 20) / ((int64_t)l1 * l2));
+  g.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 511) / 512));
+  g.rows_per_chunk = (n + g.nchunk - 1) / g.nchunk;
+  g.nchunk = (int)((n + g.rows_per_chunk - 1) / g.rows_per_chunk);
+  return g;
+}
+
+template <typename T, int L2P>
+void launch_skinny(const Gram &g, int64_t n, int l1, const T *A, int64_t lda, int l2, const T *B,
+                   int64_t ldb, double *part, hipStream_t s) {
+  gram_skinny<T, L2P><<<dim3((unsigned)g.nchunk, (unsigned)((l1 + 255) / 256)), 256, 0, s>>>(
+      n, l1, A, lda, l2, B, ldb, g.rows_per_chunk, part);
+}
+
+// Partial doubles gram() writes for an l1 x l2 product over n rows (sizes its part buffer).
+int64_t gram_part_doubles(int64_t n, int l1, int l2) {
+  const int nchunk = l2 <= 32 ? skinny_plan(n, l1, l2).nchunk : gram_plan(n).nchunk;
+  return (int64_t)nchunk * l1 * l2;
+}
+
 template <typename T>
 hipError_t gram(int64_t n, int l1, const T *A, int64_t lda, int l2, const T *B, int64_t ldb,
                 double *part, double *G, hipStream_t s) {
+  if (l2 <= 32) {
+    const Gram g = skinny_plan(n, l1, l2);
+    if (l2 == 1) launch_skinny<T, 1>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    else if (l2 <= 2) launch_skinny<T, 2>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    else if (l2 <= 4) launch_skinny<T, 4>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    else if (l2 <= 8) launch_skinny<T, 8>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    else if (l2 <= 16) launch_skinny<T, 16>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    else launch_skinny<T, 32>(g, n, l1, A, lda, l2, B, ldb, part, s);
+    const int64_t m = (int64_t)l1 * l2;
+    gram_final_wave<<<(unsigned)((m + 3) / 4), 256, 0, s>>>(g.nchunk, m, part, G);
+    return hipGetLastError();
+  }
   const Gram g = gram_plan(n);
   const int tiles = ((l1 + kGT - 1) / kGT) * ((l2 + kGT - 1) / kGT);
   gram_partial<T><<<dim3((unsigned)g.nchunk, (unsigned)tiles), 256, 0, s>>>(n, l1, A, lda, l2, B, ldb,
@@ -304,7 +390,7 @@ NysLayout nys_layout(const gp_kernel *k, int64_t n, int l) {
   L.w = o;
   o += align256(es * n * l);
   L.part = o;
-  o += align256(sizeof(double) * (size_t)gram_plan(n).nchunk * l * l);
+  o += align256(sizeof(double) * (size_t)gram_part_doubles(n, l, l));
   L.G = o;
   o += align256(sizeof(double) * l * l);
   L.M = o;
@@ -658,7 +744,7 @@ bool ranges_overlap(const void *a, int64_t rows, int64_t lda, int cols, const vo
 }  // namespace
 
 size_t nystrom_apply_scratch(int64_t n, int rank, int r) {
-  return align256(sizeof(double) * (size_t)gram_plan(n).nchunk * rank * r) +
+  return align256(sizeof(double) * (size_t)gram_part_doubles(n, rank, r)) +
          2 * align256(sizeof(double) * (size_t)rank * r);
 }
 
@@ -667,7 +753,7 @@ hipError_t nystrom_apply(int64_t n, int rank, const T *U, const double *lam, con
                          int nth, const double *shift, int r, const T *v, T *z, char *scratch,
                          hipStream_t s) {
   double *gpart = (double *)scratch;
-  double *tkc = (double *)(scratch + align256(sizeof(double) * (size_t)gram_plan(n).nchunk * rank * r));
+  double *tkc = (double *)(scratch + align256(sizeof(double) * (size_t)gram_part_doubles(n, rank, r)));
   double *M = tkc + align256(sizeof(double) * (size_t)rank * r) / sizeof(double);
   hipError_t e = gram<T>(n, rank, U, rank, r, v, r, gpart, tkc, s);
   if (e != hipSuccess) return e;
