@@ -255,7 +255,11 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
             acc = res["accepted"].cpu().numpy()
         thn = th.cpu().numpy()
         h1 = res["H1"].cpu().numpy() if mode != "plain" else None
+        # pairs evaluated by the CG products alone (one N_b^2 sweep per iteration): a lower bound
+        # on the work, since force passes, residual restarts and energies come on top
+        cg_pairs = float(np.sum(its.astype(np.float64) * np.repeat(np.asarray(ns, np.float64) ** 2, C)))
         out[mode] = {"chain_steps_per_s": len(st) * wl["n_steps"] / t, "seconds": t,
+                     "cg_pair_evals_per_s_lower_bound": cg_pairs / t,
                      "mean_cg_iters_per_solve": float(its.mean() / (wl["n_steps"] + 2)),
                      "accept_rate": float(np.mean(acc)),
                      "flagged_chains": int((st != 0).sum())}
