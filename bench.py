@@ -33,11 +33,17 @@ METRIC = "pair-evals/s for K_θV + ∇θ at N=2^20; HMC leapfrog steps/s batched
 FLOP_PER_PAIR = 143          # 4R + 3d + 6 with R = 32, d = 3 (isotropic, U = V)
 PEAK_F16_MFMA = 2.5e15       # dense fp16 matrix-core peak, FLOP/s
 PEAK_F32_VECTOR = 157.3e12   # fp32 vector peak, FLOP/s
-# VALU issue bound of the pair kernel (its ISA: 12 full-rate VALU instructions and one v_exp_f32 per
-# pair and lane; measured with paper_2412_20884_amd/probes/valu_rate.hip: 4.1 cycles per full-rate
-# wave instruction, 8.1 per v_exp_f32; 1024 SIMDs at 2.4 GHz, 64 lanes per wave)
-VALU_INSTR_PER_PAIR, VALU_CYCLES, EXP_CYCLES = 12, 4.1, 8.1
-VALU_BOUND_PAIRS = 1024 * 2.4e9 * 64 / (VALU_INSTR_PER_PAIR * VALU_CYCLES + EXP_CYCLES)
+# Issue bound of the pair kernel. Per 64-lane pair slot (one pair per lane of a wave) the SQ
+# counters of pair_mfma<3,32,1,2> on this workload count 13.62 VALU instructions besides the MFMAs
+# (11.62 plain FP32 ones, one v_exp_f32, one v_cvt_pkrtz_f16_f32) and 1.5 v_mfma_f32_16x16x32_f16.
+# paper_2412_20884_amd/probes/issue_rate.hip measures, in shader cycles per wave instruction: 2.2
+# for plain FP32 VALU with VGPR operands, 8.3 for v_exp_f32, 4.15 for v_cvt_pkrtz_f16_f32, and
+# ~16 added per MFMA when the VALU is saturated (the two do not overlap then). 1024 SIMDs at the
+# 2.4 GHz peak clock.
+SLOT_VALU, SLOT_EXP, SLOT_CVT, SLOT_MFMA = 11.62, 1.0, 1.0, 1.5
+CYC_VALU, CYC_EXP, CYC_CVT, CYC_MFMA = 2.2, 8.3, 4.15, 16.0
+SLOT_CYCLES = SLOT_VALU * CYC_VALU + SLOT_EXP * CYC_EXP + SLOT_CVT * CYC_CVT + SLOT_MFMA * CYC_MFMA
+ISSUE_BOUND_PAIRS = 1024 * 2.4e9 * 64 / SLOT_CYCLES
 
 
 def log(msg):
@@ -523,8 +529,9 @@ def main():
                      "kernel": "pair_mfma<3,32,1> (fp16 hi/lo split, 3 products per contraction)",
                      "flop_per_pair": FLOP_PER_PAIR,
                      "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR,
-                     "valu_issue_bound_pair_evals_per_s": VALU_BOUND_PAIRS,
-                     "frac_of_valu_issue_bound": pairs_per_s_kernel / VALU_BOUND_PAIRS},
+                     "issue_bound_cycles_per_pair_slot": SLOT_CYCLES,
+                     "issue_bound_pair_evals_per_s": ISSUE_BOUND_PAIRS,
+                     "frac_of_issue_bound": pairs_per_s_kernel / ISSUE_BOUND_PAIRS},
         "parity": par,
         "autotune": b["tuned"],
     }
