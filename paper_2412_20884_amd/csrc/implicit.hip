@@ -34,6 +34,12 @@ namespace {
 
 constexpr int kHistMax = 20;
 constexpr int kDotBlocks = 512;
+// Transfer block of a fixed-point iteration: the force pass's gradient, the block partials of
+// |y - A(m) x|^2 and those of the new Gram row, fetched to the host together.
+constexpr int kXfGrad = 0;
+constexpr int kXfRes = kMaxD + 4;
+constexpr int kXfRow = kXfRes + kDotBlocks;
+constexpr int kXfDoubles = kXfRow + kDotBlocks * kHistMax;
 
 // out[b][j] = partial sums over this block's rows of a[i] * H[j][i] for j < m (H rows of length n)
 template <typename T>
@@ -100,7 +106,7 @@ __global__ void scale_copy(int64_t n, const T *a, double s, T *b) {
 
 struct ImpLayout {
   size_t qf, qf_bytes, pcg, pcg_bytes, Z, AZ, x, v, rb, fx, gx, Fh, Gh, part, alpha, grad, th0,
-      nys, total;
+      xf, wts, nys, total;
 };
 
 ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
@@ -140,6 +146,10 @@ ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
   o += align256(sizeof(double) * (kMaxD + 4 + 2 + 8));
   L.th0 = o;
   o += align256(sizeof(double) * (kMaxD + 4));
+  L.xf = o;  // one device -> host transfer per fixed-point iteration (kXf* offsets)
+  o += align256(sizeof(double) * kXfDoubles);
+  L.wts = o;
+  o += align256(sizeof(double) * 2);
   L.nys = o;
   o += align256(rank > 0 ? nystrom_apply_scratch(n, rank, 1) : 0);
   L.total = o;
@@ -298,7 +308,6 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
   T *fx = (T *)(c.w + c.L.fx), *gx = (T *)(c.w + c.L.gx);
   T *Fh = (T *)(c.w + c.L.Fh), *Gh = (T *)(c.w + c.L.Gh);
   double *alpha_d = (double *)(c.w + c.L.alpha);
-  double *grad_d = (double *)(c.w + c.L.grad);
   int32_t status = 0, total_it = 0, cs = 0, ci = 0;
 
   // start: solve at theta_0 (warm), H_0
@@ -342,6 +351,17 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
   std::vector<double> th = th0, pi = pi0;
   std::vector<double> hf((size_t)kHistMax * 2 * nth), hg((size_t)kHistMax * 2 * nth);  // host parts
   std::vector<double> G((size_t)kHistMax * kHistMax);
+  // One host round trip per fixed-point iteration: the midpoint theta and the Anderson weights
+  // go up without a wait (the host buffers are not touched again before the next transfer
+  // down, which follows them on the stream), and the device work of the iteration is enqueued
+  // whole before its one transfer down.
+  const int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
+  double *xf = (double *)(c.w + c.L.xf);
+  double *wts_d = (double *)(c.w + c.L.wts);
+  const double wts[2] = {-0.5, 0.5};
+  st = h2d<T>(wts_d, wts, 2, c.s);
+  if (st) return st;
+  std::vector<double> hx(kXfDoubles), mid(nth), alpha_h(kHistMax);
   for (int step = 0; step < p.n_steps && status == 0; ++step) {
     const std::vector<double> ths = th, pis = pi;
     int m = 0, head = 0;  // history size, next slot
@@ -349,21 +369,39 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
     // the current iterate v = (th, pi, x)
     for (int it = 0; it < p.maxit; ++it) {
       ++total_it;
-      std::vector<double> mid(nth);
       for (int kx = 0; kx < nth; ++kx) mid[kx] = 0.5 * (ths[kx] + th[kx]);
-      st = h2d<T>(c.thd, mid.data(), nth, c.s);
-      if (st) return st;
+      e = hipMemcpyAsync(c.thd, mid.data(), sizeof(double) * nth, hipMemcpyHostToDevice, c.s);
+      if (e != hipSuccess) return hip_fail(e, "host -> device");
       pack_z<T><<<gb, 256, 0, c.s>>>(n, x, c.phi, Z);
-      const double wts[2] = {-0.5, 0.5};
-      st = h2d<T>(alpha_d, wts, 2, c.s);
-      if (st) return st;
-      st = gp_quadform_grad(c.k, n, c.X, c.thd, 2, Z, 2, Z, 2, alpha_d, grad_d, nullptr, AZ, 2,
+      st = gp_quadform_grad(c.k, n, c.X, c.thd, 2, Z, 2, Z, 2, wts_d, xf + kXfGrad, nullptr, AZ, 2,
                             nullptr, 0, c.w + c.L.qf, c.L.qf_bytes, c.s);
       if (st) return st;
-      std::vector<double> F(nth);
-      st = d2h(F.data(), grad_d, nth, c.s);
+      linear_residual<T><<<gb, 256, 0, c.s>>>(n, c.y, AZ, rb);
+      multi_dot<T><<<nb, 256, 0, c.s>>>(n, 1, rb, rb, n, xf + kXfRes);
+      if (c.rank > 0) {
+        e = nystrom_apply<T>(n, c.rank, (const T *)c.U, c.lam, th0_d, nth, nullptr, 1, rb, fx,
+                             c.w + c.L.nys, c.s);
+        if (e != hipSuccess) return hip_fail(e, "Nystrom apply");
+        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, fx, x, inv_c, fx, gx);
+      } else {
+        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, rb, x, inv_c, fx, gx);
+      }
+      // Anderson history: (f, g) into slot `head` and the new Gram row, ahead of the host's
+      // convergence test (a converged iteration leaves them unused)
+      const int m_new = kh > 0 ? std::min(m + 1, kh) : 0;
+      if (kh > 0) {
+        e = hipMemcpyAsync(Fh + (size_t)head * n, fx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(Gh + (size_t)head * n, gx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
+        if (e != hipSuccess) return hip_fail(e, "history");
+        multi_dot<T><<<nb, 256, 0, c.s>>>(n, m_new, fx, Fh, n, xf + kXfRow);
+      }
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "fixed-point kernels");
+      st = d2h(hx.data(), xf, kXfRow + nb * m_new, c.s);
       if (st) return st;
       // g = Phi(v), f = g - v
+      const double *F = hx.data() + kXfGrad;
       std::vector<double> g_tp(2 * nth), f_tp(2 * nth);
       double fmax = 0.0, vmax = 0.0;
       for (int kx = 0; kx < nth; ++kx) {
@@ -378,19 +416,9 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
         status |= GP_CHAIN_NONFINITE_THETA;
         break;
       }
-      linear_residual<T><<<gb, 256, 0, c.s>>>(n, c.y, AZ, rb);
-      double rr2;
-      st = dots<T>(c, rb, rb, n, 1, &rr2);
-      if (st) return st;
+      double rr2 = 0.0;
+      for (int b = 0; b < nb; ++b) rr2 += hx[(size_t)kXfRes + b];
       const double res = sqrt(rr2);  // |y - A(m) x|
-      if (c.rank > 0) {
-        e = nystrom_apply<T>(n, c.rank, (const T *)c.U, c.lam, th0_d, nth, nullptr, 1, rb, fx,
-                             c.w + c.L.nys, c.s);
-        if (e != hipSuccess) return hip_fail(e, "Nystrom apply");
-        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, fx, x, inv_c, fx, gx);
-      } else {
-        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, rb, x, inv_c, fx, gx);
-      }
       if (fmax <= p.tol * (1.0 + vmax) && res <= p.tol * ynorm) {
         conv = true;
         // take the last map value: theta_1, pi_1 from g
@@ -409,21 +437,15 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
         if (e != hipSuccess) return hip_fail(e, "copy");
         continue;
       }
-      // Anderson: store (f, g) in slot `head`, refresh the Gram row, combine
-      e = hipMemcpyAsync(Fh + (size_t)head * n, fx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(Gh + (size_t)head * n, gx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
-      if (e != hipSuccess) return hip_fail(e, "history");
+      // Anderson: the parameter parts of (f, g) in slot `head`, the Gram row, the combination
       for (int kx = 0; kx < 2 * nth; ++kx) {
         hf[(size_t)head * 2 * nth + kx] = f_tp[kx];
         hg[(size_t)head * 2 * nth + kx] = g_tp[kx];
       }
-      m = std::min(m + 1, kh);
-      double row[kHistMax];
-      st = dots<T>(c, fx, Fh, n, m, row);
-      if (st) return st;
+      m = m_new;
       for (int j = 0; j < m; ++j) {
-        double t = row[j];
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += hx[(size_t)kXfRow + (size_t)b * m + j];
         for (int kx = 0; kx < 2 * nth; ++kx) t += hf[(size_t)head * 2 * nth + kx] * hf[(size_t)j * 2 * nth + kx];
         G[(size_t)head * kHistMax + j] = t;
         G[(size_t)j * kHistMax + head] = t;
@@ -441,8 +463,9 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
         th[kx] = a;
         pi[kx] = b;
       }
-      st = h2d<T>(alpha_d, alpha.data(), m, c.s);
-      if (st) return st;
+      std::copy(alpha.begin(), alpha.end(), alpha_h.begin());
+      e = hipMemcpyAsync(alpha_d, alpha_h.data(), sizeof(double) * m, hipMemcpyHostToDevice, c.s);
+      if (e != hipSuccess) return hip_fail(e, "host -> device");
       combine<T><<<gb, 256, 0, c.s>>>(n, m, alpha_d, Gh, n, x);
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "Anderson combination");
