@@ -130,11 +130,11 @@ struct Plan {
   WsLayout L;
 };
 
-// Largest column-split count a workspace is sized for: at most 64, at least 2048 columns per
-// split, and at most 1 GiB of split partials.
+// Largest column-split count a workspace is sized for: at most 64, at least kMinSplitCols
+// columns per split, and at most 1 GiB of split partials.
 static int max_splits_for(int64_t n, int rpass) {
   int64_t m = 64;
-  if (n / 2048 < m) m = n / 2048;
+  if (n / kMinSplitCols < m) m = n / kMinSplitCols;
   const int64_t cap = ((int64_t)1 << 30) / (8 * n * (int64_t)rpass);
   if (cap < m) m = cap;
   return m < 1 ? 1 : (int)m;

@@ -70,12 +70,16 @@ struct WsLayout {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Smallest column chunk of a split: below some 32k points the row blocks alone cannot fill
+// 256 CUs, and 256 columns per block still amortise its row-side setup.
+constexpr int64_t kMinSplitCols = 256;
+
 // Column splits of the pair grid: enough blocks to fill 256 CUs several times over, with at
-// least 2048 columns per split.
+// least kMinSplitCols columns per split.
 inline int choose_splits(int64_t n, int rows_per_block) {
   int64_t rb = (n + rows_per_block - 1) / rows_per_block;
   int64_t s = (4096 + rb - 1) / rb;
-  int64_t max_s = n / 2048;
+  int64_t max_s = n / kMinSplitCols;
   if (s > max_s) s = max_s;
   if (s > 64) s = 64;
   if (s < 1) s = 1;
