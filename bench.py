@@ -172,10 +172,13 @@ def cpu_baseline(budget_s=15.0):
                       f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad"}
 
 
-def bench_leapfrog(modes=("graph", "plain"), subset=8):
+def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
     """Chain-leapfrog-steps/s on the batched workload, batched (graph replay) vs plain.
 
-    subset = k times every k-th instance (k = 1: all 64 instances).
+    subset = k takes every k-th instance (k = 1: all 64 instances). group = g > 0 runs the
+    batched modes as consecutive persistent launches over g instances each (all chains of
+    those instances), with a progress line per launch; 0 runs every instance in one launch.
+    rwm = False leaves out the random-walk Metropolis leg.
     """
     import torch
 
@@ -251,6 +254,32 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
             st = np.concatenate(sts)
             its = np.concatenate(itl)
             acc = np.concatenate(accs)
+        elif group > 0:
+            # consecutive persistent launches over `group` instances each
+            t = 0.0
+            sts, itl, accs = [], [], []
+            toff = 0
+            for g0 in range(0, len(ns), group):
+                gi = list(range(g0, min(len(ns), g0 + group)))
+                nth_g = sum(C * (ds[b] + 2) for b in gi)
+                r0, r1 = offs[gi[0]], offs[gi[-1]] + ns[gi[-1]]
+                x0_, x1_ = xoffs[gi[0]], xoffs[gi[-1]] + ns[gi[-1]] * ds[gi[-1]]
+                t0 = time.perf_counter()
+                r = gpk.hmc_leapfrog(X[x0_:x1_], y[r0:r1], phi[C * r0:C * r1], th[toff:toff + nth_g],
+                                     pi[toff:toff + nth_g], x[C * r0:C * r1], "ard", [ns[b] for b in gi],
+                                     [offs[b] - r0 for b in gi], C, d=[ds[b] for b in gi],
+                                     x_offsets=[xoffs[b] - x0_ for b in gi], u=u[gi[0] * C:(gi[-1] + 1) * C],
+                                     **kw)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+                sts.append(r["status"].cpu().numpy())
+                itl.append(r["cg_iters"].cpu().numpy())
+                accs.append(r["accepted"].cpu().numpy())
+                toff += nth_g
+                log(f"  {mode} instances {gi[0]}..{gi[-1]}: cumulative {t:.1f} s")
+            st = np.concatenate(sts)
+            its = np.concatenate(itl)
+            acc = np.concatenate(accs)
         else:
             t0 = time.perf_counter()
             res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u, **kw)
@@ -260,7 +289,6 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
             its = res["cg_iters"].cpu().numpy()
             acc = res["accepted"].cpu().numpy()
         thn = th.cpu().numpy()
-        h1 = res["H1"].cpu().numpy() if mode != "plain" else None
         # pairs evaluated by the CG products alone (one N_b^2 sweep per iteration): a lower bound
         # on the work, since force passes, residual restarts and energies come on top
         cg_pairs = float(np.sum(its.astype(np.float64) * np.repeat(np.asarray(ns, np.float64) ** 2, C)))
@@ -277,40 +305,42 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8):
         torch.cuda.empty_cache()
     if "graph" in out and "plain" in out:
         out["speedup_batched_vs_plain"] = out["graph"]["chain_steps_per_s"] / out["plain"]["chain_steps_per_s"]
-    # random-walk Metropolis on the same chains: 20 graph-mode updates, proposal scale 0.05,
-    # xi ~ N(0, I) and u ~ U(0, 1) drawn here (seeded), the solve carried as the warm start
-    n_upd, scale = 20, 0.05
-    g = np.random.default_rng(20240)
-    th = torch.tensor(th0, dtype=torch.float64, device=dev)
-    x = torch.zeros(sum(ns) * C, dtype=torch.float32, device=dev)
-    xis = torch.tensor(g.normal(size=(n_upd, th.numel())), dtype=torch.float64, device=dev)
-    us = torch.tensor(g.uniform(size=(n_upd, len(ns) * C)), dtype=torch.float64, device=dev)
-    xi = torch.empty_like(th)
-    uu = torch.empty(len(ns) * C, dtype=torch.float64, device=dev)
-    acc_n, its_n, flagged = 0, 0, 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(n_upd):
-        xi.copy_(xis[k])
-        uu.copy_(us[k])
-        r = gpk.rwm(X, y, phi, th, xi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=uu, dt=scale,
-                    cg_tol=1e-6, cg_maxit=2000, mode=gpk.GRAPH)
-        acc_n += r["accepted"].sum()
-        its_n += r["cg_iters"].sum()
-        flagged += (r["status"] != 0).sum()
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    nchain = len(ns) * C
-    out["rwm_graph"] = {"chain_updates_per_s": nchain * n_upd / t, "seconds": t, "updates": n_upd,
-                        "proposal_scale": scale, "accept_rate": float(acc_n.item()) / (nchain * n_upd),
-                        "mean_cg_iters_per_update": float(its_n.item()) / (nchain * n_upd),
-                        "flagged_chains": int(flagged.item())}
-    log(f"rwm graph: {out['rwm_graph']}")
+    if rwm:
+        # random-walk Metropolis on the same chains: 20 graph-mode updates, proposal scale 0.05,
+        # xi ~ N(0, I) and u ~ U(0, 1) drawn here (seeded), the solve carried as the warm start
+        n_upd, scale = 20, 0.05
+        g = np.random.default_rng(20240)
+        th = torch.tensor(th0, dtype=torch.float64, device=dev)
+        x = torch.zeros(sum(ns) * C, dtype=torch.float32, device=dev)
+        xis = torch.tensor(g.normal(size=(n_upd, th.numel())), dtype=torch.float64, device=dev)
+        us = torch.tensor(g.uniform(size=(n_upd, len(ns) * C)), dtype=torch.float64, device=dev)
+        xi = torch.empty_like(th)
+        uu = torch.empty(len(ns) * C, dtype=torch.float64, device=dev)
+        acc_n, its_n, flagged = 0, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_upd):
+            xi.copy_(xis[k])
+            uu.copy_(us[k])
+            r = gpk.rwm(X, y, phi, th, xi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=uu, dt=scale,
+                        cg_tol=1e-6, cg_maxit=2000, mode=gpk.GRAPH)
+            acc_n += r["accepted"].sum()
+            its_n += r["cg_iters"].sum()
+            flagged += (r["status"] != 0).sum()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        nchain = len(ns) * C
+        out["rwm_graph"] = {"chain_updates_per_s": nchain * n_upd / t, "seconds": t, "updates": n_upd,
+                            "proposal_scale": scale, "accept_rate": float(acc_n.item()) / (nchain * n_upd),
+                            "mean_cg_iters_per_update": float(its_n.item()) / (nchain * n_upd),
+                            "flagged_chains": int(flagged.item())}
+        log(f"rwm graph: {out['rwm_graph']}")
     out["phi_refresh"] = refresh
     out["workload"] = (f"batched: instances 0,{subset},{2 * subset},.. ({len(inst)} of 64; N_b in [2048, 32768], "
                        f"d_b in {{4,8,16}}), ARD SE, sigma^2=0.1, 8 chains each, {wl['n_steps']} leapfrog "
                        f"steps, dt {wl['dt']:g}, CG tol 1e-6, FP32, phi from the device Gibbs refresh; "
-                       f"N_b = {ns}, d_b = {ds}")
+                       + (f"batched modes as persistent launches over {group} instances each; " if group > 0 else "")
+                       + f"N_b = {ns}, d_b = {ds}")
     return out
 
 
@@ -484,6 +514,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--leapfrog-modes", default="graph,plain")
     ap.add_argument("--leapfrog-subset", type=int, default=16)
+    ap.add_argument("--leapfrog-group", type=int, default=0,
+                    help="instances per persistent launch in the batched modes (0: all in one)")
+    ap.add_argument("--no-rwm", action="store_true", help="leave out the random-walk Metropolis leg")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ard64", action="store_true")
@@ -539,7 +572,8 @@ def main():
         log("cpu baseline: timing the FP64 oracle on a row slab")
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     if not args.no_leapfrog:
-        line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset)
+        line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset,
+                                          args.leapfrog_group, not args.no_rwm)
     if not args.no_ard64:
         line["ard64_bf16x"] = bench_ard64()
     if not args.no_precond:
