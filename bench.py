@@ -167,7 +167,17 @@ def cpu_baseline(budget_s=15.0):
     t0 = time.perf_counter()
     ogp.quadform_grad(X, w["theta"], "iso", Z, Z, rows=rows, workers=workers)
     t = time.perf_counter() - t0
-    return {"value": m * n / t, "unit": "pair-evals/s", "cores": workers, "kind": "oracle",
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": m * n / t, "unit": "pair-evals/s", "cores": workers, "cpu_model": cpu_model,
+            "kind": "oracle",
             "sample": f"rows 0..{m - 1} of the large3 workload against all {n} columns "
                       f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad"}
 
@@ -288,6 +298,22 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
             st = res["status"].cpu().numpy()
             its = res["cg_iters"].cpu().numpy()
             acc = res["accepted"].cpu().numpy()
+        if mode != "plain":
+            # true residual |y - A(theta) x| / |y| of the solves the accepted chains return (a
+            # rejected chain gets its warm start back), A x by the FP64 product
+            worst, toff, c = 0.0, 0, 0
+            for bi in range(len(ns)):
+                nth = ds[bi] + 2
+                Xb = X[xoffs[bi]:xoffs[bi] + ns[bi] * ds[bi]].view(ns[bi], ds[bi]).double()
+                yb = y[offs[bi]:offs[bi] + ns[bi]].double()
+                for h in range(C):
+                    if acc[c]:
+                        xh = x[C * offs[bi] + h * ns[bi]:C * offs[bi] + (h + 1) * ns[bi]].double()
+                        Ax = gpk.kmatvec(Xb, th[toff + h * nth:toff + (h + 1) * nth], xh, "ard")
+                        worst = max(worst, float(torch.linalg.norm(yb - Ax) / torch.linalg.norm(yb)))
+                    c += 1
+                toff += C * nth
+            out_res = worst
         thn = th.cpu().numpy()
         # pairs evaluated by the CG products alone (one N_b^2 sweep per iteration): a lower bound
         # on the work, since force passes, residual restarts and energies come on top
@@ -297,6 +323,8 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
                      "mean_cg_iters_per_solve": float(its.mean() / (wl["n_steps"] + 2)),
                      "accept_rate": float(np.mean(acc)),
                      "flagged_chains": int((st != 0).sum())}
+        if mode != "plain":
+            out[mode]["max_true_rel_residual_accepted"] = out_res
         if ref_theta is None:
             ref_theta = thn
         else:

@@ -68,7 +68,16 @@ def test_ard64_full_size_bf16x():
     torch.cuda.synchronize()
     rows = np.random.default_rng(7).choice(n, 8, replace=False)
     ref = ogp.matvec(X, th, "ard", V, rows=rows)
-    assert _rows_rel(host(out)[rows], ref) < 3e-3
+    o = host(out)[rows]
+    assert _rows_rel(o, ref) < 3e-3
+    # the off-diagonal part (K - alpha I) V on its own: at d = 64 A is close to (alpha + sigma^2) I,
+    # so the whole product alone would meet the budget trivially (the floor of 1e-2 of the whole
+    # column as in the bfloat16 tests: the norm expansion resolves kernel entries to ~1e-5)
+    diag = np.exp(th[0]) + np.exp(th[-1])
+    od_o, od_r = o - diag * V[rows], ref - diag * V[rows]
+    num = np.linalg.norm(od_o - od_r, axis=0)
+    den = np.maximum(np.linalg.norm(od_r, axis=0), 1e-2 * np.linalg.norm(ref, axis=0))
+    assert float(np.max(num / den)) < 3e-3
     rows = np.sort(np.random.default_rng(8).choice(n, 8, replace=False))
     Vm = np.zeros_like(V)
     Vm[rows] = V[rows]
