@@ -372,7 +372,7 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
     return out
 
 
-def bench_ard64(n_chain_steps=4):
+def bench_ard64(n_chain_steps=4, chains=1, dt=None):
     """The d = 64 workload with GP_BF16X (bfloat16 cross term, compensated norms): rates of the
     product (R = 1, one CG iteration) and of the fused force pass (R = 2, [x | phi] with
     w = (-1/2, 1/2)), and one short plain-mode trajectory of one chain."""
@@ -404,24 +404,42 @@ def bench_ard64(n_chain_steps=4):
         t = float(np.median(ts))
         out[name] = {"seconds": t, "pair_evals_per_s": n * n / t}
         log(f"ard64 {name}: {out[name]}")
-    # one chain, a short trajectory (plain mode: GP_BF16X runs through the product kernels)
-    phi = gpk.phi_refresh(X, th, torch.tensor(wl["xi"][0], dtype=torch.float32, device=dev), "ard",
-                          prec="bf16x", tol=1e-6, maxit=500)
-    torch.cuda.synchronize()
-    out["phi_refresh_iterations"] = int(phi["iters"][0])
-    thc = th.clone()
-    pi = torch.tensor(wl["pi"][0], dtype=torch.float64, device=dev)
-    x = torch.zeros(n, dtype=torch.float32, device=dev)
-    t0 = time.perf_counter()
-    r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi["phi"].contiguous(), thc, pi, x, "ard", [n], [0], 1,
-                         d=[64], n_steps=n_chain_steps, dt=wl["dt"], cg_tol=1e-6, cg_maxit=500,
-                         mode=gpk.PLAIN, prec="bf16x")
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    out["trajectory"] = {"chain_steps": n_chain_steps, "seconds": t,
-                         "chain_steps_per_s": n_chain_steps / t,
-                         "cg_iterations": int(r["cg_iters"][0]), "status": int(r["status"][0]),
-                         "H0": float(r["H0"][0]), "H1": float(r["H1"][0])}
+    # trajectories chain by chain (plain mode: GP_BF16X runs through the product kernels), each
+    # after its own phi refresh, with a progress line per chain
+    t_traj, t_phi, its, acc, sts, dhs, phi_its = 0.0, 0.0, 0, 0, [], [], []
+    for h in range(chains):
+        t0 = time.perf_counter()
+        phi = gpk.phi_refresh(X, th, torch.tensor(wl["xi"][h], dtype=torch.float32, device=dev), "ard",
+                              prec="bf16x", tol=1e-6, maxit=500)
+        torch.cuda.synchronize()
+        t_phi += time.perf_counter() - t0
+        phi_its.append(int(phi["iters"][0]))
+        thc = th.clone()
+        pi = torch.tensor(wl["pi"][h], dtype=torch.float64, device=dev)
+        x = torch.zeros(n, dtype=torch.float32, device=dev)
+        u = torch.tensor([wl["u"][h]], dtype=torch.float64, device=dev) if chains > 1 else None
+        t0 = time.perf_counter()
+        r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi["phi"].contiguous(), thc, pi, x, "ard", [n], [0], 1,
+                             d=[64], u=u, n_steps=n_chain_steps, dt=dt or wl["dt"], cg_tol=1e-6, cg_maxit=500,
+                             mode=gpk.PLAIN, prec="bf16x")
+        torch.cuda.synchronize()
+        t_traj += time.perf_counter() - t0
+        its += int(r["cg_iters"][0])
+        acc += int(r["accepted"][0])
+        sts.append(int(r["status"][0]))
+        dhs.append(float(r["H1"][0]) - float(r["H0"][0]))
+        if chains > 1:
+            log(f"  ard64 chain {h}: cumulative {t_traj:.1f} s, dH {dhs[-1]:.3g}")
+    out["phi_refresh_iterations"] = phi_its[0] if chains == 1 else phi_its
+    out["trajectory"] = {"chains": chains, "chain_steps": chains * n_chain_steps, "seconds": t_traj,
+                         "chain_steps_per_s": chains * n_chain_steps / t_traj,
+                         "cg_iterations": its, "status": sts[0] if chains == 1 else sts,
+                         "dH": dhs[0] if chains == 1 else [min(dhs), max(dhs)]}
+    if chains > 1:
+        out["trajectory"]["accept_rate"] = acc / chains
+        out["trajectory"]["phi_refresh_seconds"] = t_phi
+        out["trajectory"]["workload"] = (f"{chains} chains x {n_chain_steps} leapfrog steps of dt "
+                                         f"{dt or wl['dt']:g}, one chain per call, each after its phi refresh")
     log(f"ard64 trajectory: {out['trajectory']}")
     return out
 
@@ -545,6 +563,9 @@ def main():
     ap.add_argument("--leapfrog-group", type=int, default=0,
                     help="instances per persistent launch in the batched modes (0: all in one)")
     ap.add_argument("--no-rwm", action="store_true", help="leave out the random-walk Metropolis leg")
+    ap.add_argument("--ard64-chains", type=int, default=1, help="chains of the d = 64 trajectory leg")
+    ap.add_argument("--ard64-steps", type=int, default=4, help="leapfrog steps per d = 64 trajectory")
+    ap.add_argument("--ard64-dt", type=float, default=None, help="leapfrog step of the d = 64 leg")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ard64", action="store_true")
@@ -603,7 +624,7 @@ def main():
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset,
                                           args.leapfrog_group, not args.no_rwm)
     if not args.no_ard64:
-        line["ard64_bf16x"] = bench_ard64()
+        line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt)
     if not args.no_precond:
         line["nystrom_precond"] = bench_precond()
     if not args.no_implicit:

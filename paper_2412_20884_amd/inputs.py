@@ -122,7 +122,7 @@ def ard64(n=262144, chains=16, n_steps=50):
         "xi": rng(s, P_XI).standard_normal((chains, n)),
         "pi": rng(s, P_PI).standard_normal((chains, 66)),
         "u": rng(s, P_UACC).uniform(size=chains),
-        "dt": 1e-4, "n_steps": n_steps, "chains": chains,
+        "dt": 3e-5, "n_steps": n_steps, "chains": chains,
     }
 
 
