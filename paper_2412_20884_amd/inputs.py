@@ -17,7 +17,7 @@ Workloads (shapes and distributions of the five benchmark configurations):
               noise variance of the paper's synthetic scaling runs), y = prod_k cos(x_k) +
               0.1 N(0,1); 8 chains each; 20-step trajectories of step 1e-3.
   ard64       N=262,144, X ~ N(0, I_64), ARD SE, l_k log-uniform on [0.5, 8], alpha = 1,
-              sigma^2 = 1e-2; 16 chains x 50 leapfrog steps of step 1e-4.
+              sigma^2 = 1e-2; 16 chains x 50 leapfrog steps of step 3e-5.
 """
 from __future__ import annotations
 
