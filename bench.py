@@ -485,6 +485,44 @@ def bench_precond(rank=200):
     return out
 
 
+def bench_small_fp64(tol=1e-6):
+    """The FP64 workload (N = 1024, d = 2, isotropic SE): one chain, 100 leapfrog steps of 1e-2
+    after a device phi refresh, in the plain, batched and graph modes."""
+    import torch
+
+    from paper_2412_20884_amd import gpk, inputs
+
+    dev = "cuda:0"
+    wl = inputs.small_fp64()
+    n = wl["X"].shape[0]
+    X = torch.tensor(wl["X"], dtype=torch.float64, device=dev)
+    y = torch.tensor(wl["y"], dtype=torch.float64, device=dev)
+    th0 = torch.tensor(wl["theta"], dtype=torch.float64, device=dev)
+    ph = gpk.phi_refresh(X, th0, torch.tensor(wl["xi"], dtype=torch.float64, device=dev), "iso",
+                         tol=1e-12, maxit=2000)
+    torch.cuda.synchronize()
+    phi = ph["phi"].contiguous()
+    u = torch.tensor([wl["u"]], dtype=torch.float64, device=dev)
+    out = {"workload": f"small_fp64: N={n}, d=2, iso SE, FP64, one chain, {wl['n_steps']} leapfrog "
+                       f"steps of dt {wl['dt']:g}, CG tol {tol:g}, phi by the device refresh",
+           "phi_refresh_iterations": int(ph["iters"][0])}
+    for name, mode in (("plain", gpk.PLAIN), ("batched", gpk.BATCHED), ("graph", gpk.GRAPH)):
+        th = th0.clone()
+        pi = torch.tensor(wl["pi"], dtype=torch.float64, device=dev)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi, th, pi, x, "iso", [n], [0], 1, d=[2], u=u,
+                             n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=tol, cg_maxit=3000, mode=mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"chain_steps_per_s": wl["n_steps"] / t, "seconds": t,
+                     "mean_cg_iters_per_solve": int(r["cg_iters"][0]) / (wl["n_steps"] + 2),
+                     "dH": float(r["H1"][0] - r["H0"][0]), "accepted": int(r["accepted"][0]),
+                     "status": int(r["status"][0])}
+        log(f"small_fp64 {name}: {out[name]}")
+    return out
+
+
 def bench_implicit(rank=50):
     """One chain of the batched workload's first instance: a 20-step implicit-midpoint trajectory
     (Anderson depth 10, Nystrom-based R of rank `rank`) against the plain-mode leapfrog
@@ -571,6 +609,7 @@ def main():
     ap.add_argument("--no-ard64", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-implicit", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="leave out the FP64 N = 1024 leg")
     ap.add_argument("--tune-load", default=None, help="load a saved tuning table instead of tuning")
     ap.add_argument("--tune-save", default=None, help="write the tuning table found here to this path")
     args = ap.parse_args()
@@ -629,6 +668,8 @@ def main():
         line["nystrom_precond"] = bench_precond()
     if not args.no_implicit:
         line["implicit_midpoint"] = bench_implicit()
+    if not args.no_small:
+        line["small_fp64"] = bench_small_fp64()
     print(json.dumps(line), flush=True)
 
 
