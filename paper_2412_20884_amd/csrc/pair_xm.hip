@@ -9,7 +9,10 @@
 // The K Y and S contractions run as in the fp16-split kernel (pair_mfma.hip).  For the
 // per-coordinate (ARD) gradient the identity
 //   sum_ij W_ij (x_ik - x_jk)^2 = sum_i [ x_ik^2 (W 1)_i + (W X^2)_ik - 2 x_ik (W X)_ik ]
-// turns the d sums into one more MFMA product W [X | X^2 | 1] (bf16 hi/lo, three products).
+// turns the d sums into one more MFMA product W [X | X^2 | 1]: W rounded to the nearest
+// bfloat16 and [X | X^2 | 1] split hi/lo, two products.  The same rounded W multiplies every
+// column, so the identity holds exactly for it and its zero-mean rounding averages out of the
+// sums instead of being amplified by the cancellation between the three terms.
 // Layouts are those of pair_mfma.hip: lane l = 16 g + m; A[m][8g + q], B[8g + q][m],
 // D[4g + r][m]; the k index of the products over j runs in the slot order 8g + q <-> j =
 // 16 (q / 4) + 4 g + (q % 4).
@@ -21,6 +24,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __fp16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace xm {
@@ -436,7 +440,7 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
     const bool dtile = GM != 0 && jt_cur < row0 + IB * 16 && row0 < jt_cur + TJ;
     const int doff = dtile ? (int)(row0 - jt_cur) : 0;
     H8 kh[IB], kl[IB];
-    B8 whb[IB], wlb[IB];
+    B8 whb[IB];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) {
       float kv[IB][4], wv[IB][4];
@@ -467,11 +471,10 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
           kh[ib].u[2 * jb + r / 2] = pk_rtz(h0, h1);
           kl[ib].u[2 * jb + r / 2] = pk_rtz(l0, l1);
           if (GM == 2) {
-            uint16_t a0, b0, a1, b1;
-            splitbf(wv[ib][r], a0, b0);
-            splitbf(wv[ib][r + 1], a1, b1);
-            whb[ib].u[2 * jb + r / 2] = (uint32_t)a0 | ((uint32_t)a1 << 16);
-            wlb[ib].u[2 * jb + r / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+            bf16x2 wp;  // round to nearest
+            wp[0] = (__bf16)wv[ib][r];
+            wp[1] = (__bf16)wv[ib][r + 1];
+            whb[ib].u[2 * jb + r / 2] = __builtin_bit_cast(uint32_t, wp);
           }
         }
       }
@@ -502,7 +505,6 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
           f32x4 z = wx[ib][kb];
           z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whb[ib].v, bh.v, z, 0, 0, 0);
           z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whb[ib].v, bl.v, z, 0, 0, 0);
-          z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlb[ib].v, bh.v, z, 0, 0, 0);
           wx[ib][kb] = z;
         }
       }
