@@ -335,7 +335,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     g_uploaded[ws] = upload;
     auto itg = g_graphs.find(ws);
     if (itg != g_graphs.end()) {
-      hipGraphExecDestroy(itg->second.exec);
+      (void)hipGraphExecDestroy(itg->second.exec);  // a stale graph: nothing to do on failure
       g_graphs.erase(itg);
     }
   }
@@ -411,10 +411,11 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     return GP_OK;
   }
 
+  // the defaults stand if a query fails
   int dev = 0, cus = 256, clk_khz = 100000;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
   int64_t total_jobs = 0;
   for (int c = 0; c < nc; ++c) total_jobs += (int64_t)L.n_rb[c] * L.n_cs[c];
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 4, total_jobs));
@@ -448,7 +449,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {
     if (ge.exec) {
-      hipGraphExecDestroy(ge.exec);
+      (void)hipGraphExecDestroy(ge.exec);
       ge.exec = nullptr;
     }
     hipStream_t cap;
@@ -463,9 +464,9 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     }
     if (e == hipSuccess) {
       e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
     }
-    hipStreamDestroy(cap);
+    (void)hipStreamDestroy(cap);
     if (e != hipSuccess) {
       ge.exec = nullptr;
       return hip_fail(e, "graph capture");

@@ -157,9 +157,18 @@ gp_status gp_tune_products(const gp_kernel *k, int64_t n, int32_t r, int32_t wit
   const int rpass = r < kMaxRPass ? r : kMaxRPass;
   const TuneKey key = tune_key(with_grad ? 1 : 0, k->prec, k->kind, k->d, rpass, n);
   const std::vector<TuneCfg> cands = tune_candidates(k, n, r, with_grad);
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "tuner events");
+  }
+  auto cleanup = [&] {
+    tune_force(nullptr);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  };
   TuneCfg best;
   best.ms = 1e30f;
   best.splits = 1;
@@ -168,23 +177,27 @@ gp_status gp_tune_products(const gp_kernel *k, int64_t n, int32_t r, int32_t wit
     tune_force(&c);
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
-      hipEventRecord(e0, stream);
-      gp_status st;
-      if (with_grad)
-        st = gp_quadform_grad(k, n, X, th, r, V, r, V, r, nullptr, gq, gq + nth, O, r, nullptr, 0,
-                              ws, prod, stream);
-      else
-        st = gp_kmatvec(k, n, X, th, r, V, r, nullptr, O, r, ws, prod, stream);
-      hipEventRecord(e1, stream);
+      e = hipEventRecord(e0, stream);
+      gp_status st = GP_OK;
+      if (e == hipSuccess) {
+        if (with_grad)
+          st = gp_quadform_grad(k, n, X, th, r, V, r, V, r, nullptr, gq, gq + nth, O, r, nullptr, 0,
+                                ws, prod, stream);
+        else
+          st = gp_kmatvec(k, n, X, th, r, V, r, nullptr, O, r, ws, prod, stream);
+      }
       if (st != GP_OK) {
-        tune_force(nullptr);
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        cleanup();
         return st;
       }
-      hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "tuner timing");
+      }
       if (rep > 0 && ms < ms_min) ms_min = ms;
     }
     if (ms_min < best.ms) {
@@ -192,9 +205,7 @@ gp_status gp_tune_products(const gp_kernel *k, int64_t n, int32_t r, int32_t wit
       best.ms = ms_min;
     }
   }
-  tune_force(nullptr);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  cleanup();
   tune_store(key, best);
   return GP_OK;
 }
