@@ -6,7 +6,9 @@
 // compensated norms n_i = sum_k (h_ik^2 + 2 h_ik l_ik) computed in double from the same parts,
 // so rho_ij = |x_i - x_j|^2 - |l_i - l_j|^2 (the dropped lo.lo terms cancel on the diagonal and
 // leave an error relative to the distance itself) up to float accumulation.  rho is clamped at 0.
-// The K Y and S contractions run as in the fp16-split kernel (pair_mfma.hip).  For the
+// K Y runs as in the fp16-split kernel (pair_mfma.hip); the quad weights S, which only the
+// length-scale gradient uses (through W off the diagonal), take Q rounded to the nearest
+// float16 times P hi + lo (two products: zero-mean rounding, inside the bfloat16 budget).  For the
 // per-coordinate (ARD) gradient the identity
 //   sum_ij W_ij (x_ik - x_jk)^2 = sum_i [ x_ik^2 (W 1)_i + (W X^2)_ik - 2 x_ik (W X)_ik ]
 // turns the d sums into one more MFMA product W [X | X^2 | 1]: W rounded to the nearest
@@ -66,7 +68,7 @@ __device__ __forceinline__ float bfval(uint16_t h) { return __uint_as_float((uin
 
 // A 32-column tile as stage_tiles_xm lays it out in global memory, byte for byte the image of one
 // LDS tile buffer: bf16 coordinates hi and lo (a padded row of DPX values per point), the norms,
-// with the gradient Q hi and lo (a padded row of 32 halves per point, c >= RP zero), Y^T hi and lo
+// with the gradient Q (float16, a padded row of 32 halves per point, c >= RP zero), Y^T hi and lo
 // (a padded row of 32 slot-ordered halves per column c), and for the per-coordinate gradient the
 // bf16 hi and lo of [X | X^2 | 1]^T (a padded row of 32 slot-ordered values per k2), rounded up
 // to whole 1 KB wave copies.  Every region is a multiple of 16 bytes.
@@ -82,8 +84,7 @@ struct XTile {
   static constexpr int kOffXL = kXB;
   static constexpr int kOffN = 2 * kXB;
   static constexpr int kOffQH = kOffN + kNB;
-  static constexpr int kOffQL = kOffQH + kQB;
-  static constexpr int kOffYH = kOffQL + kQB;
+  static constexpr int kOffYH = kOffQH + kQB;
   static constexpr int kOffYL = kOffYH + kYB;
   static constexpr int kOffBH = kOffYL + kYB;
   static constexpr int kOffBL = kOffBH + kBB;
@@ -221,17 +222,15 @@ __global__ __launch_bounds__(256) void stage_tiles_xm(XArgs a, int64_t ntiles) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) out.f[u] = jt + jj0 + u < a.n ? a.nrm[jt + jj0 + u] : 1.0e30f;
   } else if (off < G::kOffYH) {
-    const bool lo = off >= G::kOffQL;
-    const int o = off - (lo ? G::kOffQL : G::kOffQH);
+    const int o = off - G::kOffQH;
     const int jj = o / (2 * kStrideH), c0 = (o - jj * 2 * kStrideH) / 2;
     const int64_t j = jt + jj;
     const float sQ = ldexpf(1.0f, a.scl[3]);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int c = c0 + u;
-      float h, l;
-      split16((j < a.n && c < RP && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f, h, l);
-      out.h[u] = (_Float16)(lo ? l : h);
+      // rounded to nearest (the float16 conversion's mode)
+      out.h[u] = (_Float16)((j < a.n && c < RP && c < a.R) ? a.Q[j * a.ldq + c] * sQ : 0.0f);
     }
   } else if (off < G::kOffBH) {
     const bool lo = off >= G::kOffYL;
@@ -393,7 +392,6 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
     const uint16_t *sxl = (const uint16_t *)(cur + XT::kOffXL);
     const float *snrm = (const float *)(cur + XT::kOffN);
     const _Float16 *sqh = (const _Float16 *)(cur + XT::kOffQH);
-    const _Float16 *sql = (const _Float16 *)(cur + XT::kOffQL);
     const _Float16 *syh = (const _Float16 *)(cur + XT::kOffYH);
     const _Float16 *syl = (const _Float16 *)(cur + XT::kOffYL);
     const uint16_t *sbh = (const uint16_t *)(cur + XT::kOffBH);
@@ -419,15 +417,13 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
         }
       }
       if (GM) {
-        H8 vh, vl;
+        H8 vh;
         vh.v = *(const f16x8 *)&sqh[(16 * jb + m) * kStrideH + 8 * g];
-        vl.v = *(const f16x8 *)&sql[(16 * jb + m) * kStrideH + 8 * g];
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
           f32x4 z = {0.f, 0.f, 0.f, 0.f};
           z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, ph[ib].v, z, 0, 0, 0);
           z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vh.v, pl[ib].v, z, 0, 0, 0);
-          z = __builtin_amdgcn_mfma_f32_16x16x32_f16(vl.v, ph[ib].v, z, 0, 0, 0);
           s[ib][jb] = z;
         }
       }
