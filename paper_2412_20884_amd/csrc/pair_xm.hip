@@ -6,9 +6,11 @@
 // compensated norms n_i = sum_k (h_ik^2 + 2 h_ik l_ik) computed in double from the same parts,
 // so rho_ij = |x_i - x_j|^2 - |l_i - l_j|^2 (the dropped lo.lo terms cancel on the diagonal and
 // leave an error relative to the distance itself) up to float accumulation.  rho is clamped at 0.
-// K Y runs as in the fp16-split kernel (pair_mfma.hip); the quad weights S, which only the
-// length-scale gradient uses (through W off the diagonal), take Q rounded to the nearest
-// float16 times P hi + lo (two products: zero-mean rounding, inside the bfloat16 budget).  For the
+// K Y takes K rounded to the nearest float16 times Y hi + lo (two products) with the diagonal
+// pairs left out and alpha y_i added in double in the epilogue, so the large diagonal is exact
+// and the zero-mean rounding of the other entries stays far inside the bfloat16 budget.  The
+// quad weights S, which only the length-scale gradient uses (through W off the diagonal), take
+// Q rounded to the nearest float16 times P hi + lo (two products, the same argument).  For the
 // per-coordinate (ARD) gradient the identity
 //   sum_ij W_ij (x_ik - x_jk)^2 = sum_i [ x_ik^2 (W 1)_i + (W X^2)_ik - 2 x_ik (W X)_ik ]
 // turns the d sums into one more MFMA product W [X | X^2 | 1]: W rounded to the nearest
@@ -27,6 +29,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __fp16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace xm {
@@ -429,13 +432,14 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
       }
     }
     // ---- kernel values and gradient weights (VALU) ------------------------------------------
-    // The length-scale weights leave out the diagonal pairs: their distance is exactly zero, but
-    // the expansion x_i^2 + x_j^2 - 2 x_i x_j would cancel the large K_ii S_ii only to float
-    // rounding.  `dtile` (wave-uniform) marks the tiles that hold a diagonal pair of this wave.
+    // The diagonal pairs are left out of the tile (K_ii = alpha enters in the epilogue): their
+    // distance is exactly zero, but the expansion x_i^2 + x_j^2 - 2 x_i x_j gives it only to float
+    // rounding, and the length-scale weights would cancel the large K_ii S_ii to that rounding.
+    // `dtile` (wave-uniform) marks the tiles that hold a diagonal pair of this wave.
     const int64_t jt_cur = j0 + (int64_t)t * TJ;
-    const bool dtile = GM != 0 && jt_cur < row0 + IB * 16 && row0 < jt_cur + TJ;
+    const bool dtile = jt_cur < row0 + IB * 16 && row0 < jt_cur + TJ;
     const int doff = dtile ? (int)(row0 - jt_cur) : 0;
-    H8 kh[IB], kl[IB];
+    H8 kh[IB];
     B8 whb[IB];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) {
@@ -447,11 +451,11 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
         for (int ib = 0; ib < IB; ++ib) {
           float tt = fmaf(2.0f, C[ib][jb][r], ai[ib] - nj);
           tt = fminf(tt, c0);  // rho >= 0
-          const float kk = __builtin_amdgcn_exp2f(tt);
+          float kk = __builtin_amdgcn_exp2f(tt);
+          if (dtile && 16 * ib + m + doff == 16 * jb + 4 * g + r) kk = 0.0f;
           kv[ib][r] = kk;
           if (GM) {
-            float W = kk * s[ib][jb][r];
-            if (dtile && 16 * ib + m + doff == 16 * jb + 4 * g + r) W = 0.0f;
+            const float W = kk * s[ib][jb][r];
             if (GM == 1) gl = fmaf(W, c0 - tt, gl);
             wv[ib][r] = W;
           }
@@ -461,11 +465,10 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
       for (int ib = 0; ib < IB; ++ib) {
 #pragma unroll
         for (int r = 0; r < 4; r += 2) {
-          float h0, l0, h1, l1;
-          split16(kv[ib][r], h0, l0);
-          split16(kv[ib][r + 1], h1, l1);
-          kh[ib].u[2 * jb + r / 2] = pk_rtz(h0, h1);
-          kl[ib].u[2 * jb + r / 2] = pk_rtz(l0, l1);
+          h16x2 kp;  // round to nearest
+          kp[0] = (_Float16)kv[ib][r];
+          kp[1] = (_Float16)kv[ib][r + 1];
+          kh[ib].u[2 * jb + r / 2] = __builtin_bit_cast(uint32_t, kp);
           if (GM == 2) {
             bf16x2 wp;  // round to nearest
             wp[0] = (__bf16)wv[ib][r];
@@ -486,7 +489,6 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
         f32x4 z = acc[ib][cb];
         z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yh.v, z, 0, 0, 0);
         z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh[ib].v, yl.v, z, 0, 0, 0);
-        z = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl[ib].v, yh.v, z, 0, 0, 0);
         acc[ib][cb] = z;
       }
     }
@@ -549,6 +551,7 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
   const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   double *rec = a.rec + blk * a.nrec;
   const double sigma2 = a.no_noise ? 0.0 : exp(a.theta[a.nth - 1]);
+  const double alpha = exp(a.theta[0]);  // the diagonal kernel value, left out of the tiles
   double gA = 0.0, gS = 0.0;
   double qc[NCB];
 #pragma unroll
@@ -562,9 +565,10 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int64_t i = row0 + 16 * ib + 4 * g + r;
         if (i < a.n && c < R) {
-          const double ky = acc64[ib][cb][r] * unscale_out;
+          const double ky0 = acc64[ib][cb][r] * unscale_out;
           if (a.splits == 1) {
             const double yic = (double)a.Y[i * a.ldy + c];
+            const double ky = ky0 + alpha * yic;
             const double v = ky + (sigma2 + (a.col_shift ? a.col_shift[c] : 0.0)) * yic;
             if (a.out) a.out[i * a.ldo + c] = (float)v;
             if (a.D) {
@@ -577,7 +581,7 @@ __global__ __launch_bounds__(kWG) void pair_xm(XArgs a) {
               }
             }
           } else {
-            a.outp[((int64_t)blockIdx.y * a.n + i) * R + c] = ky;
+            a.outp[((int64_t)blockIdx.y * a.n + i) * R + c] = ky0;
           }
         }
       }
@@ -647,6 +651,7 @@ __global__ __launch_bounds__(256) void finalise_xm(XArgs a, int has_grad) {
   const bool live = i < a.n;
   const int R = a.R;
   const double sigma2 = a.no_noise ? 0.0 : exp(a.theta[a.nth - 1]);
+  const double alpha = exp(a.theta[0]);  // the diagonal kernel value, left out of the tiles
   double *rec = a.rec + (int64_t)blockIdx.x * a.nrec;
   auto bsum = [&](double v) -> double {
     v = wave_sum(v);
@@ -663,6 +668,7 @@ __global__ __launch_bounds__(256) void finalise_xm(XArgs a, int has_grad) {
       double ky = 0.0;
       for (int s = 0; s < a.splits; ++s) ky += a.outp[((int64_t)s * a.n + i) * R + c];
       const double yic = (double)a.Y[i * a.ldy + c];
+      ky += alpha * yic;
       const double v = ky + (sigma2 + (a.col_shift ? a.col_shift[c] : 0.0)) * yic;
       if (a.out) a.out[i * a.ldo + c] = (float)v;
       if (a.D) {
