@@ -614,7 +614,7 @@ def main():
     ap.add_argument("--tune-save", default=None, help="write the tuning table found here to this path")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
+        print(json.dumps({"error": "this benchmark measures one GPU only; multi-GPU sharding is a design "
                           "note (chains/instances split with no communication, large-N row shards "
                           "with a ring pass of column blocks)", "n_gpus": args.gpus}))
         sys.exit(2)
