@@ -26,7 +26,7 @@ import numpy as np
 # purpose ids: one independent stream per purpose
 P_X, P_YNOISE, P_THETA, P_V, P_U, P_PI, P_UACC, P_XI, P_SHAPE = range(9)
 
-WORKLOAD_SEEDS = {"small_fp64": 0, "ard8": 2, "large3": 3, "batched": 4, "ard64": 5}
+WORKLOAD_SEEDS = {"small_fp64": 0, "ard8": 2, "large3": 3, "batched": 4, "ard64": 5, "cheb2d": 6}
 
 
 def rng(seed, purpose):
@@ -123,6 +123,32 @@ def ard64(n=262144, chains=16, n_steps=50):
         "pi": rng(s, P_PI).standard_normal((chains, 66)),
         "u": rng(s, P_UACC).uniform(size=chains),
         "dt": 3e-5, "n_steps": n_steps, "chains": chains,
+    }
+
+
+def cheb2d(n=3000, n_cheb=4, chains=10, n_updates=10, n_steps=3, dt=0.03, ell=0.3, sigma2=0.1):
+    """Stand-in for the satellite-data run of Section 4.3: N points in [-1, 1]^2, half uniform and
+    half in 8 tight Gaussian clusters (the measurements there cluster geographically), y a
+    de-meaned smooth field plus noise; the Chebyshev-amplitude kernel with N_cheb^2 coefficients
+    (small N(0, 0.1) draws), log l and log sigma^2; B chains, each HMC update a fresh xi, pi and
+    u per chain and N_int leapfrog steps of dt."""
+    s = WORKLOAD_SEEDS["cheb2d"]
+    g = rng(s, P_X)
+    nu = n // 2
+    centres = g.uniform(-0.8, 0.8, size=(8, 2))
+    lab = g.integers(0, 8, size=n - nu)
+    X = np.concatenate([g.uniform(-1.0, 1.0, size=(nu, 2)),
+                        np.clip(centres[lab] + 0.05 * g.standard_normal((n - nu, 2)), -1.0, 1.0)])
+    y = y_sincos(0.5 * (X + 1.0), s)
+    nt = n_cheb ** 2 + 2
+    theta = np.concatenate([0.1 * rng(s, P_THETA).standard_normal(n_cheb ** 2),
+                            [np.log(ell), np.log(sigma2)]])
+    return {
+        "kind": "cheb", "n_cheb": n_cheb, "X": X, "y": y - y.mean(), "theta": theta,
+        "xi": rng(s, P_XI).standard_normal((n_updates, chains, n)),
+        "pi": rng(s, P_PI).standard_normal((n_updates, chains, nt)),
+        "u": rng(s, P_UACC).uniform(size=(n_updates, chains)),
+        "dt": dt, "n_steps": n_steps, "chains": chains, "n_updates": n_updates,
     }
 
 

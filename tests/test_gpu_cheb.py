@@ -187,3 +187,50 @@ def test_cheb_autograd_gradcheck():
                                     eps=1e-6, atol=1e-7, rtol=1e-6)
     assert torch.autograd.gradcheck(lambda t, u: ag.quadform(Xd, t, u, None, "cheb", 2), (thd, Ud),
                                     eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_cheb_plain_trajectory_two_chains_fp64():
+    """Two chains of one instance in one plain-mode call (d = 2, N_cheb = 3, 3 leapfrog steps of
+    0.03 with accept decisions) give exactly what each chain gives alone, and chain 1 follows the
+    oracle's leapfrog."""
+    n, nc, C = 300, 3, 2
+    X, th, _, _ = _problem(n, 2, nc, 21)
+    y = np.sin(3.0 * X[:, 0]) * np.cos(2.0 * X[:, 1])
+    g = np.random.default_rng([21, 502])
+    ths = [th, th + 0.05 * g.standard_normal(th.size)]
+    pis = [g.standard_normal(th.size) for _ in range(C)]
+    phis = [np.linalg.solve(np.linalg.cholesky(ogp.a_matrix(X, t, "cheb")).T, g.standard_normal(n))
+            for t in ths]
+    us = g.uniform(size=C)
+    Xd, yd = to_dev(X, torch.float64).reshape(-1, 1), to_dev(y, torch.float64)
+
+    def run(cs):
+        thd = to_dev(np.concatenate([ths[c] for c in cs]), torch.float64)
+        pid = to_dev(np.concatenate([pis[c] for c in cs]), torch.float64)
+        xd = torch.zeros(n * len(cs), dtype=torch.float64, device="cuda:0")
+        r = gpk.hmc_leapfrog(Xd, yd, to_dev(np.concatenate([phis[c] for c in cs]), torch.float64), thd,
+                             pid, xd, "cheb", [n], [0], len(cs), d=[2],
+                             u=to_dev(us[list(cs)], torch.float64), n_steps=3, dt=0.03, cg_tol=1e-12,
+                             cg_maxit=3000, mode=gpk.PLAIN, n_cheb=nc)
+        torch.cuda.synchronize()
+        return {"theta": host(thd), "pi": host(pid), "x": host(xd), "H0": host(r["H0"]),
+                "H1": host(r["H1"]), "accepted": r["accepted"].cpu().numpy(),
+                "status": r["status"].cpu().numpy(), "cg": r["cg_iters"].cpu().numpy()}
+
+    both = run([0, 1])
+    assert np.all(both["status"] == 0)
+    nt = th.size
+    for c in range(C):
+        one = run([c])
+        for key, v in one.items():
+            w = {"theta": nt, "pi": nt, "x": n}.get(key, 1)
+            np.testing.assert_array_equal(both[key][c * w:(c + 1) * w], v, err_msg=f"{key} chain {c}")
+    th1, pi1 = ohmc.leapfrog(X, "cheb", y, phis[1], ths[1], pis[1], 0.03, 3)
+    H0 = ohmc.hamiltonian(X, ths[1], "cheb", y, phis[1], pis[1])
+    H1 = ohmc.hamiltonian(X, th1, "cheb", y, phis[1], pi1)
+    assert abs(float(both["H0"][1]) - H0) < 1e-8 * abs(H0)
+    assert abs(float(both["H1"][1]) - H1) < 1e-8 * abs(H1)
+    if both["accepted"][1]:
+        assert np.max(np.abs(both["theta"][nt:] - th1)) < 1e-8
+    else:
+        np.testing.assert_array_equal(both["theta"][nt:], ths[1])
