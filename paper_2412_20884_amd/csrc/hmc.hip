@@ -359,13 +359,16 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   const bool f64 = k->prec == GP_F64;
   const size_t cb = chain_bytes(k->prec);
 
+  constexpr int kJobToDone = 6;
+  static_assert(offsetof(HmcChain<double>, done) - offsetof(HmcChain<double>, job) == kJobToDone * sizeof(int) &&
+                    offsetof(HmcChain<float>, done) - offsetof(HmcChain<float>, job) == kJobToDone * sizeof(int),
+                "the plain-mode state read assumes job .. done are adjacent ints");
   if (p->mode == GP_HMC_PLAIN) {
     for (int c = 0; c < nc; ++c) {
       void *cp = (char *)chains_dev + cb * c;
       e = f64 ? hmc_kickoff_f64(cp, 1, prm, qu, 0, stream) : hmc_kickoff_f32(cp, 1, prm, qu, 0, stream);
       if (e != hipSuccess) return hip_fail(e, "kickoff");
       const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
-      const size_t off_done = f64 ? offsetof(HmcChain<double>, done) : offsetof(HmcChain<float>, done);
       const int n_jobs = L.n_rb[c] * L.n_cs[c];
       const bool ext = uses_ext(k->prec, k->kind);
       // tile chains are checked every kPlainCheck jobs: on a finished chain the tiles and the
@@ -373,20 +376,18 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
       for (int64_t guard = 0;; ++guard) {
         if (guard > (int64_t)prm.max_jobs + 2 + kPlainCheck)
           return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
+        // job .. done are adjacent ints of the chain state: one read brings both
+        int state[kJobToDone + 1] = {};
         if (ext || guard % kPlainCheck == 0) {
-          int done = 0;
-          e = hipMemcpyAsync(&done, (char *)cp + off_done, sizeof(int), hipMemcpyDeviceToHost, stream);
+          e = hipMemcpyAsync(state, (char *)cp + off_job, sizeof(state), hipMemcpyDeviceToHost, stream);
           if (e == hipSuccess) e = hipStreamSynchronize(stream);
           if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
-          if (done) break;
+          if (state[kJobToDone]) break;
         }
         const int dpc = inst[c / chains].dp;
         if (ext) {
           // the job runs as one call of the product entry points
-          int job = 0;
-          e = hipMemcpyAsync(&job, (char *)cp + off_job, sizeof(int), hipMemcpyDeviceToHost, stream);
-          if (e == hipSuccess) e = hipStreamSynchronize(stream);
-          if (e != hipSuccess) return hip_fail(e, "plain-mode job read");
+          const int job = state[0];
           const InstInfo &in = inst[c / chains];
           gp_kernel kk = *k;
           kk.d = in.d;
@@ -406,7 +407,6 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
           e = f64 ? hmc_epilogue_f64(cp, prm, stream) : hmc_epilogue_f32(cp, prm, stream);
         if (e != hipSuccess) return hip_fail(e, "plain-mode step");
       }
-      (void)off_job;
     }
     return GP_OK;
   }
