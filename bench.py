@@ -36,7 +36,7 @@ PEAK_F32_VECTOR = 157.3e12   # fp32 vector peak, FLOP/s
 # Issue bound of the pair kernel. Per 64-lane pair slot (one pair per lane of a wave) the SQ
 # counters of pair_mfma<3,32,1,2> on this workload count 13.62 VALU instructions besides the MFMAs
 # (11.62 plain FP32 ones, one v_exp_f32, one v_cvt_pkrtz_f16_f32) and 1.5 v_mfma_f32_16x16x32_f16.
-# paper_2412_20884_amd/probes/issue_rate.hip measures, in shader cycles per wave instruction: 2.2
+# An issue-rate probe (profiles/issue_costs_gfx950.md) measured, in shader cycles per wave instruction: 2.2
 # for plain FP32 VALU with VGPR operands, 8.3 for v_exp_f32, 4.15 for v_cvt_pkrtz_f16_f32, and
 # ~16 added per MFMA when the VALU is saturated (the two do not overlap then). 1024 SIMDs at the
 # 2.4 GHz peak clock.

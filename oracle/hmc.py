@@ -8,17 +8,21 @@ Definitions followed (paper section / equation):
   * u_phi(theta, x) = S(theta) - 1/2 x^T A(theta) x + 1/2 phi^T A(theta) phi   (eq. u)
     and the force F_phi(theta) = grad_theta u_phi(theta, x) at x = x_theta with x held fixed
     (Section 3.2.1, the frozen-x evaluation).
-  * H_phi(theta, pi) = U_phi(theta) + 1/2 pi^T M^{-1} pi with M = I (Section 3.2).
+  * H_phi(theta, pi) = U_phi(theta) + 1/2 pi^T M^{-1} pi (Section 3.2).  The paper's runs use
+    M = I; a diagonal M^{-1} = diag(inv_mass) is accepted here, and a zero entry of inv_mass is
+    the limit of an infinite mass: that component of theta never moves and its momentum adds no
+    kinetic energy (used to hold a hyperparameter fixed).
   * Stormer-Verlet step (Section 3.2.2), drift-kick-drift with the force at the half step:
-        theta_1/2 = theta_0 + dt/2 * pi_0
+        theta_1/2 = theta_0 + dt/2 * M^{-1} pi_0
         pi_1      = pi_0 - dt * F(theta_1/2)
-        theta_1   = theta_1/2 + dt/2 * pi_1
+        theta_1   = theta_1/2 + dt/2 * M^{-1} pi_1
     (the printed kick has pi_1 on both sides; the reading used here starts from pi_0).
   * Metropolis test (Section 3.2, step (3); Algorithm 1): accept with probability
     min(1, exp(H_0 - H_1)); with a supplied uniform u the decision is  log u <= H_0 - H_1.
   * Random-walk Metropolis (the RWM alternative for the update of theta in Section 3; proposal
     and rule as stated at the start of Section 4): theta' = theta + dt * xi, xi ~ N(0, I),
-    accepted with probability min(1, exp(U_phi(theta) - U_phi(theta'))).
+    accepted with probability min(1, exp(U_phi(theta) - U_phi(theta'))).  With a diagonal
+    inverse mass the step is dt * sqrt(inv_mass) * xi (proposal covariance dt^2 M^{-1}).
 
 The linear solve here is an exact Cholesky solve: the oracle never iterates.  The prior is
 flat (S = 0) unless a callable is supplied.
@@ -74,21 +78,27 @@ def force(X, theta, kind, y, phi, grad_prior=None, x=None):
     return g
 
 
-def hamiltonian(X, theta, kind, y, phi, pi, prior=None):
-    """H_phi(theta, pi) = U_phi(theta) + 1/2 pi^T pi (M = I), Section 3.2."""
+def _minv(inv_mass, n):
+    return np.ones(n) if inv_mass is None else np.asarray(inv_mass, dtype=np.float64)
+
+
+def hamiltonian(X, theta, kind, y, phi, pi, prior=None, inv_mass=None):
+    """H_phi(theta, pi) = U_phi(theta) + 1/2 pi^T M^{-1} pi, Section 3.2 (M = I by default)."""
     pi = np.asarray(pi, dtype=np.float64)
-    return potential(X, theta, kind, y, phi, prior) + 0.5 * float(pi @ pi)
+    return potential(X, theta, kind, y, phi, prior) + 0.5 * float(pi @ (_minv(inv_mass, len(pi)) * pi))
 
 
-def leapfrog(X, kind, y, phi, theta0, pi0, dt, n_steps, grad_prior=None, history=False):
+def leapfrog(X, kind, y, phi, theta0, pi0, dt, n_steps, grad_prior=None, history=False,
+             inv_mass=None):
     """[S_{phi,dt}]^{n_steps}(theta0, pi0): drift-kick-drift Stormer-Verlet, Section 3.2.2."""
     theta = np.array(theta0, dtype=np.float64)
     pi = np.array(pi0, dtype=np.float64)
+    minv = _minv(inv_mass, len(pi))
     hist = []
     for _ in range(n_steps):
-        theta_half = theta + 0.5 * dt * pi
+        theta_half = theta + 0.5 * dt * (minv * pi)
         pi = pi - dt * force(X, theta_half, kind, y, phi, grad_prior)
-        theta = theta_half + 0.5 * dt * pi
+        theta = theta_half + 0.5 * dt * (minv * pi)
         if history:
             hist.append((theta.copy(), pi.copy()))
     if history:
@@ -103,15 +113,16 @@ def accept(H0, H1, u):
     return bool(np.log(u) <= H0 - H1)
 
 
-def trajectory(X, kind, y, phi, theta0, pi0, dt, n_steps, u=None, prior=None, grad_prior=None):
+def trajectory(X, kind, y, phi, theta0, pi0, dt, n_steps, u=None, prior=None, grad_prior=None,
+               inv_mass=None):
     """One HMC update of theta given phi (Algorithm 1, steps 5-10, with pi supplied).
 
     Returns dict(theta, pi, theta_prop, pi_prop, H0, H1, accepted).  With u None no
     decision is taken and the proposal is returned as accepted.
     """
-    H0 = hamiltonian(X, theta0, kind, y, phi, pi0, prior)
-    th, p = leapfrog(X, kind, y, phi, theta0, pi0, dt, n_steps, grad_prior)
-    H1 = hamiltonian(X, th, kind, y, phi, p, prior)
+    H0 = hamiltonian(X, theta0, kind, y, phi, pi0, prior, inv_mass)
+    th, p = leapfrog(X, kind, y, phi, theta0, pi0, dt, n_steps, grad_prior, inv_mass=inv_mass)
+    H1 = hamiltonian(X, th, kind, y, phi, p, prior, inv_mass)
     ok = True if u is None else accept(H0, H1, u)
     return {
         "theta": th if ok else np.array(theta0, dtype=np.float64),
@@ -124,7 +135,7 @@ def trajectory(X, kind, y, phi, theta0, pi0, dt, n_steps, u=None, prior=None, gr
     }
 
 
-def rwm_update(X, kind, y, phi, theta0, xi, dt, u=None, prior=None):
+def rwm_update(X, kind, y, phi, theta0, xi, dt, u=None, prior=None, inv_mass=None):
     """One random-walk Metropolis update of theta given phi (the RWM alternative of Section 3,
     with the proposal and acceptance rule stated at the start of Section 4): the proposal is
     theta' = theta0 + dt * xi with xi ~ N(0, I) supplied, accepted with probability
@@ -134,7 +145,7 @@ def rwm_update(X, kind, y, phi, theta0, xi, dt, u=None, prior=None):
     Returns dict(theta, theta_prop, U0, U1, accepted).
     """
     theta0 = np.asarray(theta0, dtype=np.float64)
-    prop = theta0 + dt * np.asarray(xi, dtype=np.float64)
+    prop = theta0 + dt * np.sqrt(_minv(inv_mass, len(theta0))) * np.asarray(xi, dtype=np.float64)
     U0 = potential(X, theta0, kind, y, phi, prior)
     U1 = potential(X, prop, kind, y, phi, prior)
     ok = True if u is None else accept(U0, U1, u)

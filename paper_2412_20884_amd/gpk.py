@@ -212,6 +212,28 @@ def _same(device, dtype, **ts):
             raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
 
 
+def _len_at_least(t, need, name):
+    if t is not None and t.numel() < need:
+        raise ValueError(f"{name} has {t.numel()} elements, at least {need} are needed")
+
+
+def _exact_len(t, need, name):
+    if t is not None and t.numel() != need:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {need}")
+
+
+def _shape2(t, rows, cols, name):
+    if t is not None and (t.dim() != 2 or t.shape[0] != rows or t.shape[1] != cols):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({rows}, {cols})")
+
+
+def _on_gpu(*ts):
+    # checked after every shape check, so that a mis-sized tensor is reported as such
+    for t in ts:
+        if t is not None and t.device.type != "cuda":
+            raise ValueError(f"tensors must be on a GPU device, got {t.device}")
+
+
 def workspace_size(kernel, n, r):
     return int(lib().gp_workspace_size(ctypes.byref(kernel), int(n), int(r)))
 
@@ -238,10 +260,17 @@ def kmatvec(X, theta, V, kind="iso", prec=None, col_shift=None, no_noise=False, 
     _same(dev, torch.float64, theta=theta, col_shift=col_shift)
     k = make_kernel(kind, X, prec, no_noise, n_cheb)
     n, r = X.shape[0], V2.shape[1]
+    if V2.shape[0] != n:
+        raise ValueError(f"V has {V2.shape[0]} rows, X has {n}")
+    _exact_len(theta, n_theta(kind, X.shape[1], n_cheb), "theta")
+    _exact_len(col_shift, r, "col_shift")
     if out is None:
         out = torch.empty((n, r), dtype=X.dtype, device=dev)
     out2 = out[:, None] if out.dim() == 1 else out
+    _same(dev, X.dtype, out=out2)
+    _shape2(out2, n, r, "out")
     _rowmajor(out2, "out")
+    _on_gpu(X, V2, theta, col_shift, out2)
     w = _workspace(workspace_size(k, n, r), dev, ws)
     _check(lib().gp_kmatvec(ctypes.byref(k), n, _p(X), _p(theta), r, _p(V2), V2.stride(0),
                             _p(col_shift), _p(out2), out2.stride(0), _p(w),
@@ -263,6 +292,11 @@ def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=
     k = make_kernel(kind, X, prec, no_noise, n_cheb)
     n, r = X.shape[0], U.shape[1]
     nt = n_theta(kind, X.shape[1], n_cheb)
+    _shape2(U, n, r, "U")
+    _shape2(V, n, r, "V")
+    _exact_len(theta, nt, "theta")
+    _exact_len(w, r, "w")
+    _on_gpu(X, U, V, theta, w)
     grad = torch.empty(nt, dtype=torch.float64, device=dev) if want_grad else None
     quad = torch.empty(r, dtype=torch.float64, device=dev) if want_quad else None
     AU = torch.empty((n, r), dtype=X.dtype, device=dev) if want_AU else None
@@ -276,6 +310,38 @@ def quadform_grad(X, theta, U, V=None, w=None, kind="iso", prec=None, want_grad=
 
 
 _HMC_WS = {}
+
+
+def _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chains, dims,
+                 x_offsets, n_cheb, pi_name="pi"):
+    """Lengths of the packed arrays against the batch description (packing of include/gpk.h)."""
+    n_inst = len(n_points)
+    if n_inst < 1 or len(offsets) != n_inst or len(dims) != n_inst:
+        raise ValueError("n_points, offsets and d must have one entry per instance")
+    if x_offsets is not None and len(x_offsets) != n_inst:
+        raise ValueError("x_offsets must have one entry per instance")
+    if int(chains) < 1:
+        raise ValueError("chains must be >= 1")
+    need_x = need_y = need_v = 0
+    nth_total = 0
+    for b in range(n_inst):
+        nb, ob, db = int(n_points[b]), int(offsets[b]), int(dims[b])
+        if nb < 1 or ob < 0:
+            raise ValueError(f"instance {b}: n_points must be >= 1 and offsets >= 0")
+        xo = ob * db if x_offsets is None else int(x_offsets[b])
+        need_x = max(need_x, xo + nb * db)
+        need_y = max(need_y, ob + nb)
+        need_v = max(need_v, int(chains) * (ob + nb))
+        nth_total += n_theta(kind, db, n_cheb)
+    _len_at_least(X, need_x, "X")
+    _len_at_least(y, need_y, "y")
+    _len_at_least(phi, need_v, "phi")
+    _len_at_least(x_warm, need_v, "x_warm")
+    _len_at_least(theta, int(chains) * nth_total, "theta")
+    _len_at_least(pi, int(chains) * nth_total, pi_name)
+    _len_at_least(u, n_inst * int(chains), "u")
+    _on_gpu(X, y, phi, theta, pi, x_warm, u)
+    return nth_total
 
 
 def hmc_workspace_size(kernel, params, batch):
@@ -299,6 +365,8 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
+    _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chains, dims,
+                 x_offsets, n_cheb)
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
     prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode))
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
@@ -346,6 +414,8 @@ def rwm(X, y, phi, theta, xi, x_warm, kind, n_points, offsets, chains, d=None, x
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
+    _check_batch(X, y, phi, theta, xi, x_warm, u, kind, n_points, offsets, chains, dims,
+                 x_offsets, n_cheb, pi_name="xi")
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
     prm = HmcParams(0, float(dt), float(cg_tol), int(cg_maxit), int(mode))
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
@@ -434,10 +504,16 @@ def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit
     k = make_kernel(kind, X, prec, n_cheb=n_cheb)
     prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0))
     n, r = X.shape[0], xi2.shape[1]
+    if xi2.shape[0] != n:
+        raise ValueError(f"xi has {xi2.shape[0]} rows, X has {n}")
+    _exact_len(theta, n_theta(kind, X.shape[1], n_cheb), "theta")
     if out is None:
         out = torch.empty((n, r), dtype=X.dtype, device=dev)
     out2 = out[:, None] if out.dim() == 1 else out
+    _same(dev, X.dtype, out=out2)
+    _shape2(out2, n, r, "out")
     _rowmajor(out2, "out")
+    _on_gpu(X, theta, xi2, out2)
     status = torch.empty(r, dtype=torch.int32, device=dev)
     iters = torch.empty(r, dtype=torch.int32, device=dev)
     bounds = (ctypes.c_double * 2)(0.0, 0.0)
@@ -460,6 +536,10 @@ def nystrom(X, theta, omega, kind="iso", prec=None, n_cheb=0, ws=None):
     if not omega.is_contiguous():
         raise ValueError("omega must be contiguous")
     k = make_kernel(kind, X, prec, n_cheb=n_cheb)
+    if omega.dim() != 2 or omega.shape[0] != X.shape[0]:
+        raise ValueError(f"omega must be {X.shape[0]} x rank")
+    _exact_len(theta, n_theta(kind, X.shape[1], n_cheb), "theta")
+    _on_gpu(X, theta, omega)
     n, rank = omega.shape
     U = torch.empty((n, rank), dtype=X.dtype, device=dev)
     lam = torch.empty(rank, dtype=torch.float64, device=dev)
@@ -483,9 +563,21 @@ def pcg_solve(X, theta, B, kind="iso", prec=None, x0=None, col_shift=None, U=Non
     _same(dev, torch.float64, theta=theta, col_shift=col_shift, lam=lam)
     k = make_kernel(kind, X, prec, n_cheb=n_cheb)
     n, r = B2.shape
+    if n != X.shape[0]:
+        raise ValueError(f"B has {n} rows, X has {X.shape[0]}")
     rank = 0 if U is None else U.shape[1]
     if U is not None and not U.is_contiguous():
         raise ValueError("U must be contiguous")
+    if (U is None) != (lam is None):
+        raise ValueError("U and lam go together")
+    _shape2(U, n, rank, "U")
+    _exact_len(lam, rank, "lam")
+    _exact_len(theta, n_theta(kind, X.shape[1], n_cheb), "theta")
+    _exact_len(col_shift, r, "col_shift")
+    if x0 is not None:
+        _shape2(x0[:, None] if x0.dim() == 1 else x0, n, r, "x0")
+        _same(dev, X.dtype, x0=x0)
+    _on_gpu(X, theta, B2, U, lam, col_shift, x0)
     x = torch.zeros((n, r), dtype=X.dtype, device=dev) if x0 is None else \
         (x0[:, None] if x0.dim() == 1 else x0).clone().contiguous()
     status = torch.empty(r, dtype=torch.int32, device=dev)
@@ -512,6 +604,19 @@ def hmc_implicit(X, y, phi, theta, pi, x_warm, kind="iso", n_steps=3, dt=0.1, hi
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
     k = make_kernel(kind, X, prec, n_cheb=n_cheb)
+    n = X.shape[0]
+    nt = n_theta(kind, X.shape[1], n_cheb)
+    for name, t, m in (("y", y, n), ("phi", phi, n), ("x_warm", x_warm, n), ("theta", theta, nt),
+                       ("pi", pi, nt)):
+        _exact_len(t, m, name)
+    _len_at_least(u, 1, "u")
+    if (U is None) != (lam is None):
+        raise ValueError("U and lam go together")
+    if U is not None:
+        if U.dim() != 2 or U.shape[0] != n or not U.is_contiguous():
+            raise ValueError(f"U must be a contiguous {n} x rank tensor")
+        _exact_len(lam, U.shape[1], "lam")
+    _on_gpu(X, y, phi, theta, pi, x_warm, u, U, lam)
     prm = ImplicitParams(int(n_steps), float(dt), int(history), float(tol), int(maxit), float(cg_tol),
                          int(cg_maxit), int(power_its))
     n = X.shape[0]

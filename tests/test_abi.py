@@ -203,3 +203,72 @@ def test_implicit_validation():
     prm0 = gpk.ImplicitParams(3, 0.1, 0, 1e-8, 100, 1e-6, 100, 10)
     assert L.gp_implicit_workspace_size(k, ctypes.byref(prm), 1000, 0) > \
         L.gp_implicit_workspace_size(k, ctypes.byref(prm0), 1000, 0) + 2 * 9 * 1000 * 8 - 1024
+
+
+# ---- binding-side validation (no kernel launches: CPU tensors never reach the library) ------
+
+def _t(*shape, dtype=None):
+    import torch
+    return torch.zeros(*shape, dtype=dtype or torch.float32)
+
+
+def test_binding_rejects_mis_sized_product_arguments():
+    import torch
+    X, V, th = _t(50, 3), _t(50, 4), _t(3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="rows"):
+        gpk.kmatvec(X, th, _t(49, 4))
+    with pytest.raises(ValueError, match="theta"):
+        gpk.kmatvec(X, _t(4, dtype=torch.float64), V)
+    with pytest.raises(ValueError, match="col_shift"):
+        gpk.kmatvec(X, th, V, col_shift=_t(3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="out"):
+        gpk.kmatvec(X, th, V, out=_t(50, 3))
+    with pytest.raises(TypeError, match="out"):
+        gpk.kmatvec(X, th, V, out=_t(50, 4, dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU"):
+        gpk.kmatvec(X, th, V)
+    with pytest.raises(ValueError, match="V has shape"):
+        gpk.quadform_grad(X, th, V, _t(50, 3))
+    with pytest.raises(ValueError, match="U has shape"):
+        gpk.quadform_grad(X, th, _t(40, 4))
+    with pytest.raises(ValueError, match="w has"):
+        gpk.quadform_grad(X, th, V, V, _t(3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="theta"):
+        gpk.quadform_grad(X, _t(4, dtype=torch.float64), V, kind="ard")
+    with pytest.raises(ValueError, match="GPU"):
+        gpk.quadform_grad(X, _t(5, dtype=torch.float64), V, kind="ard")
+    with pytest.raises(ValueError, match="rows"):
+        gpk.phi_refresh(X, th, _t(49, 1))
+    with pytest.raises(ValueError, match="omega"):
+        gpk.nystrom(X, th, _t(49, 5))
+    with pytest.raises(ValueError, match="lam"):
+        gpk.pcg_solve(X, th, _t(50, 2), U=_t(50, 5), lam=_t(4, dtype=torch.float64))
+    with pytest.raises(ValueError, match="B has"):
+        gpk.pcg_solve(X, th, _t(51, 2))
+
+
+def test_binding_rejects_mis_sized_trajectory_arguments():
+    import torch
+    f64 = torch.float64
+    ns, offs, chains = [30, 20], [0, 30], 3
+    X, y = _t(50, 2), _t(50)
+    phi, xw = _t(150), _t(150)
+    th, pi, u = _t(18, dtype=f64), _t(18, dtype=f64), _t(6, dtype=f64)
+
+    def call(**kw):
+        a = dict(X=X, y=y, phi=phi, theta=th, pi=pi, x_warm=xw, u=u)
+        a.update(kw)
+        return gpk.hmc_leapfrog(a["X"], a["y"], a["phi"], a["theta"], a["pi"], a["x_warm"], "iso",
+                                ns, offs, chains, u=a["u"])
+    with pytest.raises(ValueError, match="GPU"):
+        call()
+    for name, bad in (("X", _t(49, 2)), ("y", _t(49)), ("phi", _t(149)), ("x_warm", _t(149)),
+                      ("theta", _t(17, dtype=f64)), ("pi", _t(17, dtype=f64)), ("u", _t(5, dtype=f64))):
+        with pytest.raises(ValueError, match=name):
+            call(**{name: bad})
+    with pytest.raises(ValueError, match="xi"):
+        gpk.rwm(X, y, phi, th, _t(10, dtype=f64), xw, "iso", ns, offs, chains)
+    with pytest.raises(ValueError, match="one entry per instance"):
+        gpk.hmc_leapfrog(X, y, phi, th, pi, xw, "iso", ns, [0], chains)
+    with pytest.raises(ValueError, match="pi"):
+        gpk.hmc_implicit(X, y[:50], phi[:50], _t(3, dtype=f64), _t(2, dtype=f64), xw[:50])

@@ -113,12 +113,53 @@ def test_accept_rule():
 
 
 def test_trajectory_reject_restores():
+    # A downhill trajectory run backwards from its end point with the momentum negated is
+    # uphill by the same energy change (reversibility), so both Metropolis branches are reached.
     X, y, th, phi = _problem()
-    pi0 = np.array([3.0, 3.0, 3.0])
-    r = hmc.trajectory(X, "iso", y, phi, th, pi0, 0.5, 5, u=1.0 - 1e-15)
-    if r["H1"] > r["H0"]:
-        assert not r["accepted"]
-        np.testing.assert_array_equal(r["theta"], th)
+    fwd = hmc.trajectory(X, "iso", y, phi, th, np.array([3.0, 3.0, 3.0]), 0.3, 5)
+    assert fwd["H1"] < fwd["H0"] - 0.1
+    th1, pi1 = fwd["theta_prop"], -fwd["pi_prop"]
+    p_acc = math.exp(fwd["H1"] - fwd["H0"])  # acceptance probability of the uphill move
+    rej = hmc.trajectory(X, "iso", y, phi, th1, pi1, 0.3, 5, u=min(1.0, p_acc + 0.2))
+    assert rej["H1"] - rej["H0"] == pytest.approx(fwd["H0"] - fwd["H1"], abs=1e-9)
+    assert not rej["accepted"]
+    np.testing.assert_array_equal(rej["theta"], th1)
+    np.testing.assert_array_equal(rej["pi"], pi1)
+    np.testing.assert_allclose(rej["theta_prop"], th, atol=1e-10)
+    acc = hmc.trajectory(X, "iso", y, phi, th1, pi1, 0.3, 5, u=p_acc - 0.2)
+    assert acc["accepted"]
+    np.testing.assert_allclose(acc["theta"], th, atol=1e-10)
+    np.testing.assert_array_equal(acc["theta"], acc["theta_prop"])
+
+
+def test_inverse_mass_identity_and_frozen_component():
+    X, y, th, phi = _problem()
+    pi0 = np.array([0.7, -0.4, 0.9])
+    a = hmc.leapfrog(X, "iso", y, phi, th, pi0, 0.05, 4)
+    b = hmc.leapfrog(X, "iso", y, phi, th, pi0, 0.05, 4, inv_mass=np.ones(3))
+    np.testing.assert_array_equal(a[0], b[0])
+    # a zero inverse mass holds that component fixed and removes its kinetic energy
+    minv = np.array([1.0, 0.5, 0.0])
+    th1, pi1 = hmc.leapfrog(X, "iso", y, phi, th, pi0, 0.05, 4, inv_mass=minv)
+    assert th1[2] == th[2] and th1[0] != th[0] and th1[1] != th[1]
+    H = hmc.hamiltonian(X, th, "iso", y, phi, pi0, inv_mass=minv)
+    assert H == pytest.approx(hmc.potential(X, th, "iso", y, phi) + 0.5 * (0.49 + 0.5 * 0.16), abs=1e-12)
+    # with the third component frozen the flow is the M = diag(1, 2) flow of the first two with
+    # sigma^2 fixed: energy error second order in the step, reversible
+    errs = []
+    for dt, ns in ((0.04, 5), (0.02, 10)):
+        t1, p1 = hmc.leapfrog(X, "iso", y, phi, th, pi0, dt, ns, inv_mass=minv)
+        errs.append(abs(hmc.hamiltonian(X, t1, "iso", y, phi, p1, inv_mass=minv) - H))
+        tb, pb = hmc.leapfrog(X, "iso", y, phi, t1, -p1, dt, ns, inv_mass=minv)
+        np.testing.assert_allclose(tb, th, atol=1e-11)
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_rwm_inverse_mass_scales_step():
+    X, y, th, phi = _problem()
+    xi = np.array([0.3, -0.2, 0.5])
+    r = hmc.rwm_update(X, "iso", y, phi, th, xi, 0.1, inv_mass=np.array([4.0, 1.0, 0.0]))
+    np.testing.assert_allclose(r["theta_prop"] - th, [0.06, -0.02, 0.0], atol=1e-15)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3])

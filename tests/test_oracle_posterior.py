@@ -1,0 +1,110 @@
+"""Pins of the oracle's grid posterior (Section 4.1 uses a 100^2 grid on [-3, 3]^2 with the
+trapezoid rule) and of the statistics the sampler test uses (Appendix C; the DKW radius).
+
+grid_log_posterior is pinned to the pointwise log posterior (itself pinned to the N = 2 closed
+form in test_oracle_kernel) with axes of different lengths and values, so a swapped index or
+axis fails; grid_marginals to Gaussians whose marginal densities and CDFs are known in closed
+form, including a correlated one whose two marginals differ (a sum over the wrong axis fails);
+dkw_radius to the Kolmogorov-Smirnov distribution by simulation; iat_chains to AR(1) chains
+with tau = (1 + r) / (1 - r).
+"""
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+from oracle import posterior, stats
+from paper_2412_20884_amd import inputs as I
+
+
+def test_grid_log_posterior_matches_pointwise():
+    p = I.iso_problem(9, 1, 4, ell=0.4, sigma2=0.1)
+    X, y = p["X"], p["y"]
+    base = np.array([0.3, -0.2, np.log(0.1)])
+    ax0 = np.array([-1.0, 0.0, 0.7])
+    ax1 = np.array([-2.0, -0.5, 0.4, 1.1, 2.5])
+    G = posterior.grid_log_posterior(X, "iso", y, base, (0, 1), (ax0, ax1))
+    assert G.shape == (3, 5)
+    for a, va in enumerate(ax0):
+        for b, vb in enumerate(ax1):
+            th = np.array([va, vb, np.log(0.1)])
+            assert G[a, b] == pytest.approx(posterior.log_posterior(X, th, "iso", y), abs=1e-12)
+    # the first component moves along rows: rows differ, and so do columns
+    assert np.all(np.abs(np.diff(G, axis=0)) > 1e-6) and np.all(np.abs(np.diff(G, axis=1)) > 1e-6)
+    # idx selects the components: (1, 0) is the transpose on swapped axes
+    Gt = posterior.grid_log_posterior(X, "iso", y, base, (1, 0), (ax1, ax0))
+    np.testing.assert_allclose(Gt, G.T, atol=1e-12)
+
+
+def test_trapezoid_weights_integrate_linear_exactly():
+    x = np.array([-1.0, -0.2, 0.5, 2.0])
+    w = posterior.trapezoid_weights(x)
+    assert w.sum() == pytest.approx(3.0)
+    assert w @ (2 * x + 1) == pytest.approx((4.0 + 2.0) - (1.0 - 1.0))
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.6])
+def test_grid_marginals_of_gaussian(rho):
+    mu = np.array([0.4, -0.8])
+    s = np.array([0.5, 0.9])
+    ax0 = np.linspace(mu[0] - 9 * s[0], mu[0] + 9 * s[0], 801)
+    ax1 = np.linspace(mu[1] - 9 * s[1], mu[1] + 9 * s[1], 1001)
+    a, b = np.meshgrid((ax0 - mu[0]) / s[0], (ax1 - mu[1]) / s[1], indexing="ij")
+    logp = -(a * a - 2 * rho * a * b + b * b) / (2 * (1 - rho * rho)) + 5.0
+    (m0, m1), (c0, c1) = posterior.grid_marginals(logp, (ax0, ax1))
+    np.testing.assert_allclose(m0, norm.pdf(ax0, mu[0], s[0]), atol=2e-4)
+    np.testing.assert_allclose(m1, norm.pdf(ax1, mu[1], s[1]), atol=2e-4)
+    np.testing.assert_allclose(c0, norm.cdf(ax0, mu[0], s[0]), atol=1e-4)
+    np.testing.assert_allclose(c1, norm.cdf(ax1, mu[1], s[1]), atol=1e-4)
+    assert c0[-1] == pytest.approx(1.0, abs=1e-9) and c1[-1] == pytest.approx(1.0, abs=1e-9)
+
+
+def test_dkw_radius_coverage_by_simulation():
+    # sup |F_n - F| of n uniforms exceeds the radius with probability close to (and at most)
+    # delta: DKW with Massart's constant is tight for the Kolmogorov-Smirnov tail
+    g = np.random.default_rng(7)
+    n, reps, delta = 200, 4000, 0.05
+    r = stats.dkw_radius(n, delta)
+    u = np.sort(g.uniform(size=(reps, n)), axis=1)
+    i = np.arange(1, n + 1)
+    D = np.maximum(np.max(i / n - u, axis=1), np.max(u - (i - 1) / n, axis=1))
+    frac = np.mean(D > r)
+    assert 0.025 < frac < 0.06, frac
+    assert stats.dkw_radius(4 * n, delta) == pytest.approx(r / 2)
+
+
+@pytest.mark.parametrize("r", [0.0, 0.5, 0.8])
+def test_iat_chains_ar1(r):
+    g = np.random.default_rng(11)
+    B, L = 200, 2000
+    x = np.empty((B, L))
+    x[:, 0] = g.normal(size=B)
+    e = g.normal(size=(B, L)) * np.sqrt(1 - r * r)
+    for t in range(1, L):
+        x[:, t] = r * x[:, t - 1] + e[:, t]
+    tau = stats.iat_chains(x + 3.0, max_lag=200)
+    want = (1 + r) / (1 - r)
+    assert abs(tau - want) < 0.08 * want + 0.05, (tau, want)
+    # one chain through iat_chains is iat
+    assert stats.iat_chains(x[0], max_lag=L - 1) == pytest.approx(stats.iat(x[0]))
+
+
+def test_e1_golden_is_the_oracle_grid_posterior():
+    # the committed fixture is exactly what the oracle's grid posterior gives for the E1 problem
+    import json
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    try:
+        import make_golden
+    finally:
+        sys.path.remove(here)
+    spec, X, y, axis = make_golden.e1_data()
+    gold = json.load(open(os.path.join(here, "e1_grid_marginals.json")))
+    base = np.array([0.0, 0.0, np.log(spec["sigma2"])])
+    logp = posterior.grid_log_posterior(X, "iso", y, base, (0, 1), (axis, axis))
+    (m0, m1), (c0, c1) = posterior.grid_marginals(logp, (axis, axis))
+    np.testing.assert_allclose(gold["axis"], axis, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(gold["cdf_log_alpha"], c0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(gold["cdf_log_l"], c1, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(gold["marginal_log_alpha"], m0, rtol=1e-13, atol=1e-15)
