@@ -118,6 +118,27 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
                      void *out, int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * gp_kmatvec_noalloc -- gp_kmatvec for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that must not call hipMalloc, harnesses that forbid it).
+ *
+ * Same product, arguments and validation as gp_kmatvec, without a workspace argument: the
+ * workspace is a 64 MiB array in device memory that the library holds on every device it runs
+ * on until the process ends; it makes no allocation of its own.  The column-split count of the
+ * pass is reduced until the workspace fits, so results equal gp_kmatvec's up to the order of
+ * floating-point sums.  A product whose workspace cannot fit in 64 MiB returns GP_ERR_WORKSPACE
+ * before anything is enqueued; the limit is set by the staged column tiles of the matrix-core
+ * passes: about 170,000 points for GP_F32 with 8 <= r <= 32 and d <= 16, about 37,000 for
+ * GP_BF16X at d = 64, and 2 to 4 million for the VALU passes (GP_F64, or r < 8).  The first call on a device looks up the array's device address
+ * (a HIP runtime query, no allocation).
+ * Calls on one device share the array: two calls whose work overlaps on the device (different
+ * streams, or host threads without ordering) race on it and give undefined results.  Calls
+ * ordered on one stream are safe; no state carries over from one call to the next.
+ */
+gp_status gp_kmatvec_noalloc(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                             int32_t r, const void *V, int64_t ldv, const double *col_shift,
+                             void *out, int64_t ldo, hipStream_t stream);
+
+/*
  * gp_quadform_grad -- Q = sum_c w_c u_c^T A(theta) v_c, its theta-gradient and A U, A V in one
  * pass over the pairs.
  *

@@ -143,7 +143,20 @@ static int max_splits_for(int64_t n, int rpass) {
 static thread_local bool t_forced = false;
 static thread_local TuneCfg t_force_cfg;
 
-static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
+static WsLayout plan_layout(const gp_kernel *k, const Plan &pl, int64_t n) {
+  const int rows_min = pl.use_mfma ? kRowsMfmaMin : kRowsValu;
+  const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.max_splits;
+  const int64_t fb = pl.max_splits > 1 ? (n + kThreads - 1) / kThreads : 0;
+  const size_t scr = pl.use_mfma == 2 ? xm_scratch_bytes(n, k->d)
+                     : pl.use_mfma    ? mfma_scratch_bytes(n, pl.dp)
+                                      : 0;
+  return ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec, scr);
+}
+
+// Plan of a product pass.  With cap > 0 the workspace must fit in cap bytes: the column-split
+// count (the only size that is a choice) is halved until it does; if one split does not fit,
+// pl.L.total is left above cap.
+static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op, size_t cap = 0) {
   Plan pl;
   pl.dp = padded_dim(k->d);
   pl.rpass = r < kMaxRPass ? r : kMaxRPass;
@@ -151,6 +164,10 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
   pl.use_mfma = k->prec == GP_BF16X ? 2 : (mfma_supported(k->prec, k->kind, k->d, pl.rpass) ? 1 : 0);
   const int rows = pl.use_mfma ? kRowsMfma : kRowsValu;
   pl.max_splits = max_splits_for(n, pl.rpass);
+  pl.nrec = nth_of(k) + pl.rpass;
+  if (cap > 0) {
+    while (pl.max_splits > 1 && plan_layout(k, pl, n).total > cap) pl.max_splits /= 2;
+  }
   pl.splits = choose_splits(n, rows);
   if (pl.splits > pl.max_splits) pl.splits = pl.max_splits;
   pl.ib = 2;
@@ -166,14 +183,7 @@ static Plan make_plan(const gp_kernel *k, int64_t n, int r, int op) {
     pl.splits = c.splits < 1 ? 1 : (c.splits > pl.max_splits ? pl.max_splits : c.splits);
     pl.ib = c.ib == 1 ? 1 : 2;
   }
-  pl.nrec = nth_of(k) + pl.rpass;
-  const int rows_min = pl.use_mfma ? kRowsMfmaMin : kRowsValu;
-  const int64_t pb = ((n + rows_min - 1) / rows_min) * pl.max_splits;
-  const int64_t fb = pl.max_splits > 1 ? (n + kThreads - 1) / kThreads : 0;
-  const size_t scr = pl.use_mfma == 2 ? xm_scratch_bytes(n, k->d)
-                     : pl.use_mfma    ? mfma_scratch_bytes(n, pl.dp)
-                                      : 0;
-  pl.L = ws_layout(n, pl.dp, elem_size(k->prec), pl.rpass, pl.max_splits, pb, fb, pl.nrec, scr);
+  pl.L = plan_layout(k, pl, n);
   return pl;
 }
 
@@ -253,10 +263,16 @@ size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
   return make_plan(k, n, r, -1).L.total;
 }
 
-gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double *theta,
-                     int32_t r, const void *V, int64_t ldv, const double *col_shift, void *out,
-                     int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream) {
-  clear_error();
+}  // extern "C"
+
+namespace gpk {
+
+// gp_kmatvec with the workspace planned to fit cap bytes (cap = 0: the full plan).  dry: every
+// check (the workspace fit included, the workspace pointer excluded) and no HIP call.
+gp_status kmatvec_run(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                      int32_t r, const void *V, int64_t ldv, const double *col_shift, void *out,
+                      int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream, size_t cap,
+                      bool dry) {
   gp_status st = check_kernel(k, true);
   if (st) return st;
   if (n < 0) return fail(GP_ERR_SHAPE, "n = %lld < 0", (long long)n);
@@ -268,9 +284,18 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
                 (long long)ldv, (long long)ldo, r);
   const size_t es = elem_size(k->prec);
   if (overlap(V, n, ldv, r, out, n, ldo, r, es)) return fail(GP_ERR_ARG, "out overlaps V");
-  if (k->kind == GP_SE_CHEB)
+  if (k->kind == GP_SE_CHEB) {
+    if (cap > 0 && cheb_workspace_size(k, n, r) > cap)
+      return fail(GP_ERR_WORKSPACE, "the product needs %zu bytes of workspace, the limit is %zu",
+                  cheb_workspace_size(k, n, r), cap);
+    if (dry) return GP_OK;
     return cheb_kmatvec(k, n, X, theta, r, V, ldv, col_shift, out, ldo, ws, ws_bytes, stream);
-  const Plan pl = make_plan(k, n, r, 0);
+  }
+  const Plan pl = make_plan(k, n, r, 0, cap);
+  if (cap > 0 && pl.L.total > cap)
+    return fail(GP_ERR_WORKSPACE, "the product needs %zu bytes of workspace, the limit is %zu",
+                pl.L.total, cap);
+  if (dry) return GP_OK;
   if (!ws || ws_bytes < pl.L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -296,6 +321,18 @@ gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double 
     if (e != hipSuccess) return hip_fail(e, "kmatvec pass");
   }
   return GP_OK;
+}
+
+}  // namespace gpk
+
+extern "C" {
+
+gp_status gp_kmatvec(const gp_kernel *k, int64_t n, const void *X, const double *theta,
+                     int32_t r, const void *V, int64_t ldv, const double *col_shift, void *out,
+                     int64_t ldo, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  return kmatvec_run(k, n, X, theta, r, V, ldv, col_shift, out, ldo, ws, ws_bytes, stream, 0,
+                     false);
 }
 
 gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const double *theta,

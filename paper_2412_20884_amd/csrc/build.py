@@ -30,7 +30,7 @@ FLAGS = [
 
 SOURCES = ["api.hip", "pair_valu_f32.hip", "pair_valu_f64.hip", "pair_mfma.hip", "hmc.hip",
            "hmc_f32.hip", "hmc_f64.hip", "tune.hip", "pair_xm.hip", "poles.hip", "cheb.hip",
-           "nystrom.hip", "implicit.hip"]
+           "nystrom.hip", "implicit.hip", "noalloc.hip"]
 
 
 def _compile(src):

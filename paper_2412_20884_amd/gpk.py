@@ -28,7 +28,7 @@ EXPORTED = (
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
     "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
     "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve", "gp_implicit_workspace_size",
-    "gp_hmc_implicit", "gp_rwm",
+    "gp_hmc_implicit", "gp_rwm", "gp_kmatvec_noalloc",
 )
 
 
@@ -92,6 +92,9 @@ def lib():
     L.gp_kmatvec.restype = _i32
     L.gp_kmatvec.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp, _vp,
                              _i64, _vp, _sz, _vp]
+    L.gp_kmatvec_noalloc.restype = _i32
+    L.gp_kmatvec_noalloc.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp,
+                                     _vp, _i64, _vp]
     L.gp_quadform_grad.restype = _i32
     L.gp_quadform_grad.argtypes = [ctypes.POINTER(Kernel), _i64, _vp, _vp, _i32, _vp, _i64, _vp,
                                    _i64, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp]

@@ -272,3 +272,21 @@ def test_binding_rejects_mis_sized_trajectory_arguments():
         gpk.hmc_leapfrog(X, y, phi, th, pi, xw, "iso", ns, [0], chains)
     with pytest.raises(ValueError, match="pi"):
         gpk.hmc_implicit(X, y[:50], phi[:50], _t(3, dtype=f64), _t(2, dtype=f64), xw[:50])
+
+
+def test_kmatvec_noalloc_validates_before_any_hip_call():
+    # argument errors and a workspace that cannot fit the library's 64 MiB array are reported
+    # with no HIP call (so this runs on a CPU-only host); empty products succeed
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+
+    def call(k, n, r=16, X=1 << 40, V=3 << 40, out=4 << 40):
+        return L.gp_kmatvec_noalloc(k, n, vp(X), vp(2 << 40), r, vp(V), r, None, vp(out), r, None)
+    iso32 = ctypes.byref(gpk.Kernel(gpk.ISO, gpk.F32, 3, 0))
+    assert call(None, 10) == 1
+    assert call(iso32, 10, X=0) == 1
+    assert call(iso32, 10, V=4 << 40, out=4 << 40) == 1
+    assert call(iso32, 400000) == 4
+    assert b"limit" in L.gp_last_error()
+    assert call(ctypes.byref(gpk.Kernel(gpk.ARD, gpk.BF16X, 64, 0)), 60000, r=1) == 4
+    assert call(iso32, 0) == 0 and call(iso32, 10, r=0) == 0
