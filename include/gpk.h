@@ -188,13 +188,35 @@ gp_status gp_tune_load(const char *path);
 int32_t gp_tune_entries(void);
 void gp_tune_clear(void);
 
-/* Trajectory parameters. */
+/* Trajectory parameters.
+ *
+ * inv_mass: the diagonal of M^{-1} in H = U_phi + 1/2 pi^T M^{-1} pi (Section 3.2; the paper's
+ * runs use M = I).  Host array packed per instance like one chain's theta (instance b's n_theta_b
+ * entries at the sum of n_theta over the instances before it), shared by the instance's chains;
+ * entries finite and >= 0.  A zero entry is the limit of an infinite mass: that component of theta
+ * stays fixed and its momentum adds no kinetic energy (a hyperparameter held at its value).
+ * NULL: M = I.
+ *
+ * precond_rank, precond_U, precond_lam: an optional randomized Nystrom factor K ~ U diag(lam) U^T
+ * per instance (gp_nystrom's output; Section 3.1 after eq. pex, rank 5 in Section 4.1 and 500 in
+ * Section 4.3) with which every conjugate-gradient solve of the trajectory is preconditioned by
+ * P^{-1} = U diag((lam_rank + mu) / (lam + mu)) U^T + (I - U U^T), mu = sigma^2 at the theta of
+ * the solve (the Woodbury form of gp_pcg_solve).  precond_U: device, kernel precision, instance
+ * b's n_b x rank block (row-major, orthonormal columns) at element offset offsets[b] * rank;
+ * precond_lam: device double, instance b's rank values (descending, >= 0) at b * rank.  The factor
+ * may come from any theta (for example the chains' current one): the solves converge to the same
+ * tolerance with any factor, only the iteration count depends on it.  precond_rank = 0: plain CG.
+ */
 typedef struct {
   int32_t n_steps;  /* leapfrog steps per trajectory, N_int >= 0 */
   double dt;        /* step size */
   double cg_tol;    /* relative residual |y - A x|_2 / |y|_2 at which CG stops, > 0 */
   int32_t cg_maxit; /* CG iteration limit per solve, >= 1 */
   int32_t mode;     /* GP_HMC_PLAIN, GP_HMC_BATCHED or GP_HMC_GRAPH */
+  const double *inv_mass;    /* host, packed per instance, or NULL (M = I) */
+  int32_t precond_rank;      /* 0..512; rank <= n_b for every instance */
+  const void *precond_U;     /* device, packed per instance, or NULL when precond_rank = 0 */
+  const double *precond_lam; /* device, packed per instance, or NULL when precond_rank = 0 */
 } gp_hmc_params;
 
 enum {
@@ -226,7 +248,8 @@ size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const g
 
 /*
  * gp_hmc_leapfrog -- one HMC trajectory of theta given phi for every chain: the Hamiltonian
- * H = U_phi(theta) + 1/2 pi^T pi (Section 3.2, eq. U, M = I), n_steps drift-kick-drift
+ * H = U_phi(theta) + 1/2 pi^T M^{-1} pi (Section 3.2, eq. U; M^{-1} = diag(p->inv_mass), or I),
+ * n_steps drift-kick-drift
  * Stormer-Verlet steps (Section 3.2.2) with the force of Section 3.2.1 (solve A x = y by
  * conjugate gradients warm-started from x_warm, then the frozen-x gradient of eq. (u) as one
  * quadratic-form pass), and the Metropolis decision of Algorithm 1 (steps 6-10).
@@ -259,7 +282,8 @@ gp_status gp_hmc_leapfrog(const gp_kernel *k, const gp_hmc_params *p, const gp_b
  * theta' = theta + dt * xi, with xi ~ N(0, I) drawn by the caller, is accepted when
  * log u <= U_phi(theta) - U_phi(theta').  Both energies U_phi (eq. U, without a kinetic term) come
  * from one conjugate-gradient solve warm-started from x_warm and one quadratic-form pass each,
- * exactly as the end-point energies of gp_hmc_leapfrog.  Parameters, batch packing, workspace
+ * exactly as the end-point energies of gp_hmc_leapfrog.  With p->inv_mass the step is
+ * dt * sqrt(inv_mass) * xi (proposal covariance dt^2 M^{-1}; a zero entry holds that component).  Parameters, batch packing, workspace
  * (gp_hmc_workspace_size) and modes are those of gp_hmc_leapfrog; p->n_steps is ignored and
  * p->dt is the proposal scale.
  *

@@ -15,6 +15,7 @@ enum HmcCtxKind { kCtxEnergy0 = 0, kCtxForce = 1, kCtxEnergy1 = 2 };
 constexpr int kHmcRec = 72;        // doubles per tile record: [0..7] scalars, [8 + k] gradient
 constexpr int kHmcTile = 256;      // rows per tile (one per thread)
 constexpr int kHmcMaxTheta = kMaxD + 2;
+constexpr int kHmcMaxRank = 512;   // largest Nystrom rank of the preconditioned solves
 
 template <typename T>
 struct HmcChain {
@@ -37,6 +38,11 @@ struct HmcChain {
   double *qpart;  // n_cs x n partial products (n_cs > 1 only)
   double *rec;    // n_jobs x kHmcRec
   double theta0[kHmcMaxTheta], pi0[kHmcMaxTheta], F[kHmcMaxTheta];
+  double minv[kHmcMaxTheta];  // diagonal of the inverse mass matrix
+  // Nystrom preconditioner of the solves (prank = 0: plain CG): U n x prank, lam prank
+  const T *pU;
+  const double *plam;
+  int prank;
   double centre[kMaxD];
   // schedule
   int n_rb, n_cs, n_jobs;
@@ -51,6 +57,7 @@ struct HmcChain {
   int done;
   int jobs_run;  // jobs completed in this trajectory (bounded, see HmcRunParams::max_jobs)
   double rr, yy, H0, H1;
+  double rz;  // r^T z of the preconditioned CG (z = P^{-1} r)
   // External products (GP_BF16X, plain mode): the jobs run as gp_kmatvec / gp_quadform_grad
   // passes that write q in full, or the force and the two forms into ext_res.
   int ext;

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -21,14 +22,14 @@ hipError_t hmc_kickoff_f32(void *, int, const HmcRunParams &, const HmcQueue &, 
 hipError_t hmc_kickoff_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
 hipError_t hmc_tiles_f32(void *, int, int, hipStream_t);
 hipError_t hmc_tiles_f64(void *, int, int, hipStream_t);
-hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, hipStream_t);
-hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, hipStream_t);
+hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, int, hipStream_t);
+hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, int, hipStream_t);
 hipError_t hmc_gather_f32(void *, int, hipStream_t);
 hipError_t hmc_gather_f64(void *, int, hipStream_t);
 hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, hipStream_t);
+                              int, int, hipStream_t);
 hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, hipStream_t);
+                              int, int, hipStream_t);
 hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
 hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
 hipError_t hmc_check_f32(void *, int, hipStream_t);
@@ -39,7 +40,10 @@ namespace {
 struct InstInfo {
   int64_t n, off, xoff;
   int d, dp, nth;
+  int64_t tofs;  // sum of n_theta over the instances before this one
 };
+
+constexpr int kMaxPrecondRank = kHmcMaxRank;
 
 struct ChainLayout {
   size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains, prod, prod_bytes;
@@ -142,8 +146,12 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   if (b->n_inst < 1 || b->chains_per_inst < 1)
     return fail(GP_ERR_SHAPE, "n_inst and chains_per_inst must be >= 1");
   if (!b->n_points || !b->offsets) return fail(GP_ERR_ARG, "n_points and offsets are required");
+  if (p->precond_rank < 0 || p->precond_rank > kMaxPrecondRank)
+    return fail(GP_ERR_ARG, "precond_rank = %d outside 0..%d", p->precond_rank, kMaxPrecondRank);
+  if (p->precond_rank > 0 && (!p->precond_U || !p->precond_lam))
+    return fail(GP_ERR_ARG, "precond_U and precond_lam are required when precond_rank > 0");
   inst.clear();
-  int64_t xo = 0;
+  int64_t xo = 0, tofs = 0;
   for (int i = 0; i < b->n_inst; ++i) {
     InstInfo in;
     in.n = b->n_points[i];
@@ -166,6 +174,19 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
     }
     in.xoff = b->x_offsets ? b->x_offsets[i] : in.off * in.d;
     if (in.xoff < 0) return fail(GP_ERR_SHAPE, "instance %d has a negative x offset", i);
+    if (p->precond_rank > in.n)
+      return fail(GP_ERR_SHAPE, "precond_rank %d exceeds instance %d's %lld points",
+                  p->precond_rank, i, (long long)in.n);
+    in.tofs = tofs;
+    if (p->inv_mass) {
+      for (int t = 0; t < in.nth; ++t) {
+        const double m = p->inv_mass[tofs + t];
+        if (!(m >= 0.0) || !std::isfinite(m))
+          return fail(GP_ERR_ARG, "inv_mass[%lld] = %g is not finite and >= 0",
+                      (long long)(tofs + t), m);
+      }
+    }
+    tofs += in.nth;
     (void)xo;
     inst.push_back(in);
   }
@@ -181,7 +202,7 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
 
 template <typename T>
 void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const ChainLayout &L,
-                 char *ws,
+                 char *ws, const gp_hmc_params *p,
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
                  int32_t *status, int32_t *iters, int ext, std::vector<HmcChain<T>> &out) {
@@ -207,6 +228,12 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const 
       ch.acc_out = acc + c;
       ch.status_out = status + c;
       ch.iters_out = iters ? iters + c : nullptr;
+      for (int t = 0; t < in.nth; ++t) ch.minv[t] = p->inv_mass ? p->inv_mass[in.tofs + t] : 1.0;
+      ch.prank = p->precond_rank;
+      if (ch.prank > 0) {
+        ch.pU = (const T *)p->precond_U + in.off * (int64_t)ch.prank;
+        ch.plam = p->precond_lam + (int64_t)b * ch.prank;
+      }
       ch.n = in.n;
       ch.d = in.d;
       ch.dp = in.dp;
@@ -301,12 +328,12 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   std::vector<char> desc;
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
-    fill_chains<double>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+    fill_chains<double>(inst, k->kind, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
                         accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
-    fill_chains<float>(inst, k->kind, chains, L, w, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+    fill_chains<float>(inst, k->kind, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
                        accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
@@ -357,6 +384,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   qu.order = (unsigned *)(w + L.hdr_order);
   void *chains_dev = w + L.chains;
   const bool f64 = k->prec == GP_F64;
+  const int pc = p->precond_rank > 0 ? 1 : 0;
   const size_t cb = chain_bytes(k->prec);
 
   constexpr int kJobToDone = 6;
@@ -404,7 +432,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
             e = f64 ? hmc_gather_f64(cp, L.n_rb[c], stream) : hmc_gather_f32(cp, L.n_rb[c], stream);
         }
         if (e == hipSuccess)
-          e = f64 ? hmc_epilogue_f64(cp, prm, stream) : hmc_epilogue_f32(cp, prm, stream);
+          e = f64 ? hmc_epilogue_f64(cp, prm, pc, stream) : hmc_epilogue_f32(cp, prm, pc, stream);
         if (e != hipSuccess) return hip_fail(e, "plain-mode step");
       }
     }
@@ -430,8 +458,8 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
             : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, s)
-            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, s);
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, s)
+            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, s);
     if (r != hipSuccess) return r;
     return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
   };
@@ -446,6 +474,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   std::vector<char> key((const char *)&prm, (const char *)(&prm + 1));
   key.insert(key.end(), (const char *)&grid, (const char *)(&grid + 1));
   key.insert(key.end(), (const char *)&dpmax, (const char *)(&dpmax + 1));
+  key.insert(key.end(), (const char *)&pc, (const char *)(&pc + 1));
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {
     if (ge.exec) {

@@ -45,7 +45,9 @@ class Kernel(ctypes.Structure):
 
 class HmcParams(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int32), ("dt", ctypes.c_double), ("cg_tol", ctypes.c_double),
-                ("cg_maxit", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("cg_maxit", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("inv_mass", ctypes.POINTER(ctypes.c_double)), ("precond_rank", ctypes.c_int32),
+                ("precond_U", ctypes.c_void_p), ("precond_lam", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -347,14 +349,74 @@ def _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chain
     return nth_total
 
 
+def _chain_outputs(outputs, names, nc, dev, cg_iters):
+    """Per-chain output tensors: the caller's (a dict from an earlier call, so that graph mode
+    replays with unchanged descriptors) or new ones."""
+    if outputs is not None:
+        o = outputs
+        for key, dt in ((names[0], torch.float64), (names[1], torch.float64),
+                        ("accepted", torch.int32), ("status", torch.int32)):
+            t = o[key]
+            if t.dtype != dt or t.numel() != nc or t.device != dev or not t.is_contiguous():
+                raise ValueError(f"outputs[{key!r}] must be a contiguous {dt} tensor of {nc} on {dev}")
+        it = o.get("cg_iters")
+        if it is not None and (it.dtype != torch.int32 or it.numel() != nc or it.device != dev):
+            raise ValueError("outputs['cg_iters'] must be an int32 tensor of one entry per chain")
+        return o[names[0]], o[names[1]], o["accepted"], o["status"], it
+    return (torch.empty(nc, dtype=torch.float64, device=dev),
+            torch.empty(nc, dtype=torch.float64, device=dev),
+            torch.empty(nc, dtype=torch.int32, device=dev),
+            torch.empty(nc, dtype=torch.int32, device=dev),
+            torch.empty(nc, dtype=torch.int32, device=dev) if cg_iters else None)
+
+
+def _hmc_params(n_steps, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_total, n_points,
+                offsets, X):
+    """gp_hmc_params; inv_mass: host sequence (one instance's n_theta, or all instances' packed),
+    precond: (U, lam) tensors packed per instance (gp_hmc_params in include/gpk.h), or None.
+    Returns (params, keep-alive objects)."""
+    keep = []
+    im = None
+    if inv_mass is not None:
+        vals = [float(v) for v in (inv_mass.tolist() if hasattr(inv_mass, "tolist") else inv_mass)]
+        if len(vals) != nth_total:
+            raise ValueError(f"inv_mass has {len(vals)} entries, the batch has {nth_total}")
+        im = (ctypes.c_double * nth_total)(*vals)
+        keep.append(im)
+    rank, pU, plam = 0, None, None
+    if precond is not None:
+        U, lam = precond
+        if U.dim() != 2 or not U.is_contiguous() or not lam.is_contiguous():
+            raise ValueError("precond U must be a contiguous 2-D tensor (rows x rank)")
+        rank = U.shape[1]
+        _same(X.device, X.dtype, precond_U=U)
+        _same(X.device, torch.float64, precond_lam=lam)
+        need_u = max(int(o) + int(n) for o, n in zip(offsets, n_points))
+        _len_at_least(U, need_u * rank, "precond U")
+        _len_at_least(lam, len(n_points) * rank, "precond lam")
+        _on_gpu(U, lam)
+        pU, plam = _p(U), _p(lam)
+    prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode),
+                    ctypes.cast(im, ctypes.POINTER(ctypes.c_double)) if im is not None else None,
+                    int(rank), pU, plam)
+    return prm, keep
+
+
 def hmc_workspace_size(kernel, params, batch):
     return int(lib().gp_hmc_workspace_size(ctypes.byref(kernel), ctypes.byref(params), ctypes.byref(batch)))
 
 
 def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, d=None,
                  x_offsets=None, u=None, n_steps=20, dt=1e-2, cg_tol=1e-6, cg_maxit=1000,
-                 mode=BATCHED, ws=None, cg_iters=True, prec=None, n_cheb=0):
+                 mode=BATCHED, ws=None, cg_iters=True, prec=None, n_cheb=0, inv_mass=None,
+                 precond=None, outputs=None):
     """One HMC trajectory per chain through gp_hmc_leapfrog (packing as in include/gpk.h).
+
+    inv_mass: host sequence, the diagonal of M^{-1} packed per instance (None: M = I; a zero
+    entry holds that hyperparameter fixed).  precond: (U, lam), a Nystrom factor per instance
+    packed as in gp_hmc_params, with which every solve is preconditioned (None: plain CG).
+    outputs: the dict an earlier call returned, to be written again (graph mode then replays its
+    captured launch without a new capture).
 
     theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, cg_iters).
     The workspace is kept per (device, size) so repeated calls reuse it (and a captured graph).
@@ -368,21 +430,18 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
-    _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chains, dims,
-                 x_offsets, n_cheb)
+    nth_total = _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chains,
+                             dims, x_offsets, n_cheb)
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
-    prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode))
+    prm, _keep = _hmc_params(n_steps, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_total,
+                             n_points, offsets, X)
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
     offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
     dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
     xo = (ctypes.c_int64 * n_inst)(*[int(v) for v in x_offsets]) if x_offsets is not None else None
     b = Batch(n_inst, int(chains), npts, offs, dd, xo)
     nc = n_inst * chains
-    H0 = torch.empty(nc, dtype=torch.float64, device=dev)
-    H1 = torch.empty(nc, dtype=torch.float64, device=dev)
-    acc = torch.empty(nc, dtype=torch.int32, device=dev)
-    st = torch.empty(nc, dtype=torch.int32, device=dev)
-    it = torch.empty(nc, dtype=torch.int32, device=dev) if cg_iters else None
+    H0, H1, acc, st, it = _chain_outputs(outputs, ("H0", "H1"), nc, dev, cg_iters)
     nbytes = hmc_workspace_size(k, prm, b)
     if nbytes == 0:
         _check(lib().gp_hmc_leapfrog(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, None,
@@ -402,7 +461,7 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
 
 def rwm(X, y, phi, theta, xi, x_warm, kind, n_points, offsets, chains, d=None, x_offsets=None,
         u=None, dt=0.1, cg_tol=1e-6, cg_maxit=1000, mode=BATCHED, ws=None, cg_iters=True,
-        prec=None, n_cheb=0):
+        prec=None, n_cheb=0, inv_mass=None, precond=None, outputs=None):
     """One random-walk Metropolis update per chain through gp_rwm (packing as in include/gpk.h):
     proposal theta + dt * xi, accepted when log u <= U0 - U1.
 
@@ -417,21 +476,18 @@ def rwm(X, y, phi, theta, xi, x_warm, kind, n_points, offsets, chains, d=None, x
             raise ValueError(f"{name} must be contiguous")
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
-    _check_batch(X, y, phi, theta, xi, x_warm, u, kind, n_points, offsets, chains, dims,
-                 x_offsets, n_cheb, pi_name="xi")
+    nth_total = _check_batch(X, y, phi, theta, xi, x_warm, u, kind, n_points, offsets, chains,
+                             dims, x_offsets, n_cheb, pi_name="xi")
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
-    prm = HmcParams(0, float(dt), float(cg_tol), int(cg_maxit), int(mode))
+    prm, _keep = _hmc_params(0, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_total,
+                             n_points, offsets, X)
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
     offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
     dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
     xo = (ctypes.c_int64 * n_inst)(*[int(v) for v in x_offsets]) if x_offsets is not None else None
     b = Batch(n_inst, int(chains), npts, offs, dd, xo)
     nc = n_inst * chains
-    U0 = torch.empty(nc, dtype=torch.float64, device=dev)
-    U1 = torch.empty(nc, dtype=torch.float64, device=dev)
-    acc = torch.empty(nc, dtype=torch.int32, device=dev)
-    st = torch.empty(nc, dtype=torch.int32, device=dev)
-    it = torch.empty(nc, dtype=torch.int32, device=dev) if cg_iters else None
+    U0, U1, acc, st, it = _chain_outputs(outputs, ("U0", "U1"), nc, dev, cg_iters)
     nbytes = hmc_workspace_size(k, prm, b)
     if nbytes == 0:
         _check(lib().gp_rwm(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, None, None,

@@ -26,7 +26,7 @@ def phi_exact(X, th, kind, xi):
     return solve_triangular(L.T, xi, lower=False)
 
 
-def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None):
+def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None, precond=None):
     """insts: list of dict(X, y, theta, phi[chains], pi[chains], x0[chains])."""
     ns = [len(b["y"]) for b in insts]
     offs = np.cumsum([0] + ns[:-1])
@@ -44,7 +44,7 @@ def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None):
     ud = None if u is None else to_dev(u, torch.float64)
     res = gpk.hmc_leapfrog(Xd, to_dev(y, dtype), to_dev(phi, dtype), thd, pid, xd, kind, ns, offs,
                            chains, d=ds, x_offsets=xoffs, u=ud, n_steps=n_steps, dt=dt,
-                           cg_tol=tol, cg_maxit=maxit, mode=mode)
+                           cg_tol=tol, cg_maxit=maxit, mode=mode, precond=precond)
     torch.cuda.synchronize()
     out = {k: (v.cpu().numpy() if v.dtype == torch.int32 else host(v))
            for k, v in res.items() if v is not None}

@@ -1,0 +1,142 @@
+"""Trajectories with a diagonal inverse mass and with Nystrom-preconditioned solves against the
+FP64 oracle (exact Cholesky solves, no preconditioner), in the three scheduling modes.
+
+The preconditioner changes only how the solves converge: trajectories must match the oracle as the
+unpreconditioned ones do, with fewer CG iterations.  The factor is the library's own (gp_nystrom at
+the start theta, Gaussian test matrix drawn here), one per instance, packed at offsets[b] * rank.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hmc as ohmc
+from paper_2412_20884_amd import gpk
+from paper_2412_20884_amd import inputs as I
+from gpu_util import DEV, host, rounded, to_dev
+from test_gpu_hmc import phi_exact, run, single
+
+pytestmark = pytest.mark.gpu
+
+MODES = [gpk.PLAIN, gpk.BATCHED, gpk.GRAPH]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_inverse_mass_trajectory_matches_oracle(mode):
+    p = I.iso_problem(500, 2, 17, ell=0.3, sigma2=0.05)
+    X, y, th = p["X"], p["y"], p["theta"]
+    phi = phi_exact(X, th, "iso", p["xi"])
+    pi0 = np.array([0.6, -0.4, 0.7])
+    minv = np.array([2.0, 0.5, 0.0])
+    Xd = to_dev(X, torch.float64)
+    thd, pid = to_dev(th, torch.float64), to_dev(pi0, torch.float64)
+    xd = torch.zeros(500, dtype=torch.float64, device=DEV)
+    r = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float64), to_dev(phi, torch.float64), thd, pid, xd,
+                         "iso", [500], [0], 1, n_steps=6, dt=0.04, cg_tol=1e-12, cg_maxit=5000,
+                         mode=mode, inv_mass=minv)
+    torch.cuda.synchronize()
+    th1, pi1 = ohmc.leapfrog(X, "iso", y, phi, th, pi0, 0.04, 6, inv_mass=minv)
+    H0 = ohmc.hamiltonian(X, th, "iso", y, phi, pi0, inv_mass=minv)
+    H1 = ohmc.hamiltonian(X, th1, "iso", y, phi, pi1, inv_mass=minv)
+    assert r["status"].item() == 0
+    assert np.max(np.abs(host(thd) - th1)) < 1e-8 and np.max(np.abs(host(pid) - pi1)) < 1e-8
+    assert host(thd)[2] == th[2]
+    assert abs(r["H0"].item() - H0) < 1e-8 * abs(H0) and abs(r["H1"].item() - H1) < 1e-8 * abs(H1)
+
+
+def test_rwm_inverse_mass_matches_oracle():
+    p = I.iso_problem(400, 2, 18, ell=0.3, sigma2=0.05)
+    X, y, th = p["X"], p["y"], p["theta"]
+    phi = phi_exact(X, th, "iso", p["xi"])
+    xi = np.array([0.5, -1.0, 2.0])
+    minv = np.array([4.0, 1.0, 0.0])
+    Xd = to_dev(X, torch.float64)
+    thd, xid = to_dev(th, torch.float64), to_dev(xi, torch.float64)
+    xd = torch.zeros(400, dtype=torch.float64, device=DEV)
+    r = gpk.rwm(Xd, to_dev(y, torch.float64), to_dev(phi, torch.float64), thd, xid, xd, "iso",
+                [400], [0], 1, dt=0.1, cg_tol=1e-12, cg_maxit=5000, mode=gpk.BATCHED,
+                inv_mass=minv)
+    torch.cuda.synchronize()
+    ref = ohmc.rwm_update(X, "iso", y, phi, th, xi, 0.1, inv_mass=minv)
+    np.testing.assert_allclose(host(thd), ref["theta_prop"], rtol=0, atol=1e-14)
+    assert abs(r["U1"].item() - ref["U1"]) < 1e-8 * abs(ref["U1"])
+
+
+def _factor(X, th, kind, rank, dtype, seed):
+    Xd = to_dev(X, dtype)
+    om = to_dev(np.random.default_rng(seed).standard_normal((len(X), rank)), dtype)
+    U, lam = gpk.nystrom(Xd, to_dev(th, torch.float64), om, kind)
+    torch.cuda.synchronize()
+    return host(U), host(lam)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_preconditioned_trajectories_match_oracle(dtype, mode):
+    chains, rank, steps, dt = 2, 24, 4, 0.02
+    specs = [("iso", 900, 2, 0.4), ("iso", 1300, 2, 0.25)]
+    insts, Us, lams = [], [], []
+    for s, (kind, n, d, ell) in enumerate(specs):
+        # FP64 at sigma^2 = 2e-3 (condition ~1e5); float32 solves are accurate to ~1e-4 in the
+        # residual only, so the float32 case runs the better-conditioned sigma^2 = 1e-2
+        p = I.iso_problem(n, d, 60 + s, ell=ell, sigma2=2e-3 if dtype == torch.float64 else 1e-2)
+        X, y = rounded(p["X"], dtype), rounded(p["y"], dtype)
+        g = np.random.default_rng(70 + s)
+        phis = [rounded(phi_exact(X, p["theta"], "iso", g.normal(size=n)), dtype) for _ in range(chains)]
+        pis = [g.normal(size=3) * 0.5 for _ in range(chains)]
+        insts.append({"X": X, "y": y, "theta": p["theta"], "phi": phis, "pi": pis,
+                      "x0": [np.zeros(n)] * chains})
+        U, lam = _factor(X, p["theta"], "iso", rank, dtype, 80 + s)
+        Us.append(U)
+        lams.append(lam)
+    Ud = to_dev(np.concatenate(Us), dtype)
+    lamd = to_dev(np.concatenate(lams), torch.float64)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    r0 = run(insts, "iso", dtype, chains, steps, dt, tol, mode, maxit=20000)
+    r1 = run(insts, "iso", dtype, chains, steps, dt, tol, mode, maxit=20000, precond=(Ud, lamd))
+    assert np.all(r0["status"] == 0) and np.all(r1["status"] == 0)
+    it0, it1 = r0["cg_iters"], r1["cg_iters"]
+    print(f"CG iterations per trajectory, plain {it0.tolist()} vs preconditioned {it1.tolist()}")
+    assert np.all(it1 < 0.6 * it0), (it0, it1)
+    # FP64: both runs match the oracle's exact-solve trajectory to 1e-8.  Float32: solves reach
+    # the 1e-6 recurrence residual but not a 1e-6 true residual at these condition numbers, so the
+    # preconditioned run must be as close to the oracle as the plain-CG run is (and within 1e-3)
+    err = {0: 0.0, 1: 0.0}
+    herr = {0: 0.0, 1: 0.0}
+    pos = c = 0
+    for b in insts:
+        for h in range(chains):
+            th1, pi1 = ohmc.leapfrog(b["X"], "iso", b["y"], b["phi"][h], b["theta"], b["pi"][h], dt, steps)
+            H1 = ohmc.hamiltonian(b["X"], th1, "iso", b["y"], b["phi"][h], pi1)
+            for key, rr in ((0, r0), (1, r1)):
+                e = max(np.max(np.abs(rr["theta"][pos:pos + 3] - th1)),
+                        np.max(np.abs(rr["pi"][pos:pos + 3] - pi1) / np.maximum(1.0, np.abs(pi1))))
+                err[key] = max(err[key], e)
+                herr[key] = max(herr[key], abs(rr["H1"][c] - H1) / max(1.0, abs(H1)))
+            pos += 3
+            c += 1
+    print(f"max error vs oracle: plain CG {err[0]:.2e} (H1 {herr[0]:.2e}), "
+          f"preconditioned {err[1]:.2e} (H1 {herr[1]:.2e})")
+    if dtype == torch.float64:
+        assert err[1] < 1e-8 and err[0] < 1e-8 and herr[1] < 1e-8
+        bound = 1e-8
+    else:
+        assert err[1] <= 2.0 * err[0] + 1e-4 and err[1] < 1e-3 and herr[1] < 1e-4
+        bound = 1e-3
+    # the same states as the unpreconditioned run, up to the solve tolerance
+    np.testing.assert_allclose(r1["theta"], r0["theta"], rtol=0, atol=bound)
+    np.testing.assert_array_equal(r1["accepted"], r0["accepted"])
+
+
+def test_preconditioner_rejected_when_malformed():
+    X = torch.zeros((50, 2), dtype=torch.float64, device=DEV)
+    y = torch.zeros(50, dtype=torch.float64, device=DEV)
+    th = torch.zeros(3, dtype=torch.float64, device=DEV)
+    U = torch.zeros((50, 60), dtype=torch.float64, device=DEV)
+    lam = torch.zeros(60, dtype=torch.float64, device=DEV)
+    with pytest.raises(gpk.GpkError):  # rank above the instance's point count
+        gpk.hmc_leapfrog(X, y, y, th, th.clone(), y.clone(), "iso", [50], [0], 1,
+                         precond=(torch.zeros((50, 51), dtype=torch.float64, device=DEV),
+                                  torch.zeros(51, dtype=torch.float64, device=DEV)))
+    with pytest.raises(gpk.GpkError):  # a negative inverse mass
+        gpk.hmc_leapfrog(X, y, y, th, th.clone(), y.clone(), "iso", [50], [0], 1,
+                         inv_mass=[1.0, -1.0, 1.0], precond=(U[:, :5].contiguous(), lam[:5]))
