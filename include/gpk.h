@@ -325,6 +325,9 @@ typedef struct {
   double tol;         /* relative residual |xi - (A + lambda_p I) x_p| / |xi| of every pole, > 0 */
   int32_t maxit;      /* iteration limit, >= 1 */
   double lambda_max;  /* M >= lambda_max(A); <= 0: the Gershgorin bound max_i (A 1)_i is used */
+  int32_t precond_rank;      /* 0: multi-shift CG; 1..512: Nystrom-preconditioned CG per pole */
+  const void *precond_U;     /* device n x rank (gp_nystrom's U), kernel precision, or NULL */
+  const double *precond_lam; /* device rank values (gp_nystrom's lam), or NULL */
 } gp_phi_params;
 
 /* Bytes of workspace gp_phi_refresh needs; 0 for an invalid description or n = 0. */
@@ -333,10 +336,14 @@ size_t gp_phi_workspace_size(const gp_kernel *k, const gp_phi_params *p, int64_t
 /*
  * gp_phi_refresh -- phi = A(theta)^{-1/2} xi for r right-hand sides at once.
  *
- * The lower spectral bound is m = sigma^2 (read from theta).  All N_p shifted systems are solved
- * together by multi-shift conjugate gradients on A: one product with A per iteration for every
- * right-hand side, the shifted iterates following from the unshifted CG scalars; phi accumulates
- * sum_p w_p x_p directly.  Iteration stops per column once every pole's residual is below tol.
+ * The lower spectral bound is m = sigma^2 (read from theta).  Without a preconditioner all N_p
+ * shifted systems are solved together by multi-shift conjugate gradients on A: one product with A
+ * per iteration for every right-hand side, the shifted iterates following from the unshifted CG
+ * scalars; phi accumulates sum_p w_p x_p directly.  With a Nystrom factor (precond_rank > 0; the
+ * factor of K at any theta, reused across the shifts as Section 3.1 describes) the shifted systems
+ * of each column are solved as one batch of preconditioned CG columns by gp_pcg_solve (the
+ * preconditioner of A + lambda_p I uses mu = sigma^2 + lambda_p), then combined; iters reports the
+ * largest pole's count.  Iteration stops per column once every pole's residual is below tol.
  * The host checks convergence every few iterations; the call synchronises `stream`.
  *
  *   X         device, n x d, kernel precision (GP_NO_NOISE is rejected: no lower bound m)

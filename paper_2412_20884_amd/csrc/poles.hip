@@ -44,6 +44,7 @@ namespace {
 constexpr int kPoleMax = 64;     // most poles per call
 constexpr int kPhiMaxR = 32;     // most right-hand sides per call
 constexpr int kCheckEvery = 4;   // host convergence check period, iterations
+constexpr int kPcgBatch = 32;    // pole columns per preconditioned batch (gp_pcg_solve's limit)
 
 // ---- Jacobi elliptic functions by the AGM (host) ---------------------------------------------
 
@@ -407,6 +408,38 @@ __global__ void fill_value(T *a, int64_t m, T v) {
   if (e < m) a[e] = v;
 }
 
+// Preconditioned path: column c of xi replicated into the npc pole columns of b (n x npc).
+template <typename T>
+__global__ void phi_replicate(int64_t n, int npc, const T *xi, int64_t ldxi, int c, T *b) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * npc) b[e] = xi[(e / npc) * ldxi + c];
+}
+
+// phi_ic (+)= sum_p w_p x_ip over one batch of pole columns (fixed order in p), in double.
+template <typename T>
+__global__ void phi_combine(int64_t n, int npc, const T *x, const double *w, T *phi, int64_t ldphi,
+                            int c, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = first ? 0.0 : (double)phi[i * ldphi + c];
+  for (int p = 0; p < npc; ++p) s += w[p] * (double)x[i * npc + p];
+  phi[i * ldphi + c] = (T)s;
+}
+
+// Column status: the OR of the poles' bits (GP_CG_* and GP_PHI_* share their values), iterations
+// the largest pole's.
+__global__ void phi_pole_status(int npc, const int32_t *pst, const int32_t *pit, int32_t *status,
+                                int32_t *iters, int c, int first) {
+  if (threadIdx.x != 0) return;
+  int32_t s = 0, it = 0;
+  for (int p = 0; p < npc; ++p) {
+    s |= pst[p];
+    it = pit[p] > it ? pit[p] : it;
+  }
+  if (status) status[c] = first ? s : (status[c] | s);
+  if (iters) iters[c] = first ? it : (iters[c] > it ? iters[c] : it);
+}
+
 // ---- workspace --------------------------------------------------------------------------------
 
 struct PhiLayout {
@@ -419,10 +452,13 @@ struct PhiLayout {
   size_t shift;     // PoleShift [r][np]
   size_t wl;        // double [2][np] weights, shifts
   size_t remaining; // int32
+  // preconditioned path: PCG workspace, replicated right-hand side and solutions (T [n][npc]),
+  // per-pole status and iterations
+  size_t pcg = 0, pcg_bytes = 0, pb = 0, px = 0, pst = 0;
   size_t total;
 };
 
-PhiLayout phi_layout(const gp_kernel *k, int64_t n, int r, int np) {
+PhiLayout phi_layout(const gp_kernel *k, int64_t n, int r, int np, int rank) {
   PhiLayout L;
   const size_t es = k->prec == GP_F64 ? 8 : 4;
   const size_t p1 = gp_workspace_size(k, n, 1), pr = gp_workspace_size(k, n, r);
@@ -430,8 +466,21 @@ PhiLayout phi_layout(const gp_kernel *k, int64_t n, int r, int np) {
   size_t o = 0;
   L.prod = o;
   o += align256(L.prod_bytes);
+  if (rank > 0) {
+    // preconditioned: one batch of pole columns at a time (no shifted directions kept)
+    const int npc = np < kPcgBatch ? np : kPcgBatch;
+    L.pcg_bytes = gp_pcg_workspace_size(k, n, npc, rank);
+    L.pcg = o;
+    o += align256(L.pcg_bytes);
+    L.pb = o;
+    o += align256(es * (size_t)n * npc);
+    L.px = o;
+    o += align256(es * (size_t)n * npc);
+    L.pst = o;
+    o += align256(2 * sizeof(int32_t) * kPcgBatch);
+  }
   L.ps = o;
-  o += align256(es * (size_t)np * n * r);
+  o += rank > 0 ? 0 : align256(es * (size_t)np * n * r);
   L.rv = o;
   o += align256(es * (size_t)n * r);
   L.pv = o;
@@ -518,6 +567,37 @@ gp_status run_phi(const gp_kernel *k, const gp_phi_params *pp, int64_t n, const 
   e = hipMemcpyAsync(wl, hw.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "uploading the pole weights");
 
+  if (pp->precond_rank > 0) {
+    // Nystrom-preconditioned CG for the shifted systems of each column, then phi = sum_p w_p x_p
+    const int rank = pp->precond_rank;
+    T *pb = (T *)(ws + L.pb), *px = (T *)(ws + L.px);
+    int32_t *pst = (int32_t *)(ws + L.pst), *pit = pst + kPcgBatch;
+    const double *w_dev = wl, *shift_dev = wl + np;
+    const int nb = np < kPcgBatch ? np : kPcgBatch;  // width of the replicated right-hand side
+    for (int c = 0; c < r; ++c) {
+      // xi's column is read once, before any batch writes phi (which may be xi itself)
+      phi_replicate<T><<<(unsigned)((n * nb + 255) / 256), 256, 0, stream>>>(n, nb, xi, ldxi, c, pb);
+      for (int p0 = 0; p0 < np; p0 += kPcgBatch) {
+        const int npc = np - p0 < kPcgBatch ? np - p0 : kPcgBatch;
+        const unsigned eb = (unsigned)((n * npc + 255) / 256);
+        fill_value<T><<<eb, 256, 0, stream>>>(px, n * npc, (T)0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "preconditioned phi set-up");
+        st = gp_pcg_solve(k, n, X, theta, npc, pb, nb, px, npc, shift_dev + p0, rank,
+                          pp->precond_U, pp->precond_lam, pp->tol, pp->maxit, pst, pit,
+                          ws + L.pcg, L.pcg_bytes, stream);
+        if (st) return st;
+        phi_combine<T><<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, npc, px, w_dev + p0, phi,
+                                                                       ldphi, c, p0 == 0);
+        phi_pole_status<<<1, 64, 0, stream>>>(npc, pst, pit, status, iters, c, p0 == 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "preconditioned phi combine");
+      }
+    }
+    e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? GP_OK : hip_fail(e, "phi finish");
+  }
+
   const VecGrid g = vec_grid(n, r);
   const unsigned vb = (unsigned)g.blocks;
   phi_init<T><<<vb, kThreads, 0, stream>>>(n, r, g, xi, ldxi, rv, pv, phi, ldphi, part);
@@ -561,6 +641,10 @@ gp_status check_phi(const gp_kernel *k, const gp_phi_params *p, int64_t n, int32
   if (p->maxit < 1) return fail(GP_ERR_ARG, "maxit must be >= 1");
   if (!(p->lambda_max <= 0.0 || isfinite(p->lambda_max)))
     return fail(GP_ERR_ARG, "lambda_max must be finite");
+  if (p->precond_rank < 0 || p->precond_rank > 512 || (n > 0 && p->precond_rank > n))
+    return fail(GP_ERR_SHAPE, "precond_rank = %d outside 0..min(n, 512)", p->precond_rank);
+  if (p->precond_rank > 0 && (!p->precond_U || !p->precond_lam))
+    return fail(GP_ERR_ARG, "precond_rank > 0 needs precond_U and precond_lam");
   return GP_OK;
 }
 
@@ -600,7 +684,7 @@ gp_status gp_pole_weights(double m, double M, int32_t n_poles, double *w, double
 
 size_t gp_phi_workspace_size(const gp_kernel *k, const gp_phi_params *p, int64_t n, int32_t r) {
   if (check_phi(k, p, n, r) != GP_OK || n == 0) return 0;  // n = 0 needs no workspace
-  return phi_layout(k, n, r, p->n_poles).total;
+  return phi_layout(k, n, r, p->n_poles, p->precond_rank).total;
 }
 
 gp_status gp_phi_refresh(const gp_kernel *k, const gp_phi_params *p, int64_t n, const void *X,
@@ -618,7 +702,7 @@ gp_status gp_phi_refresh(const gp_kernel *k, const gp_phi_params *p, int64_t n, 
   if (n > 0 && !(xi == phi && ldxi == ldphi) && ranges_overlap(xi, n, ldxi, r, phi, ldphi, es))
     return fail(GP_ERR_ARG, "phi overlaps xi (only phi == xi with equal leading dimensions is allowed)");
   if (n > 0 && ranges_overlap(X, n, k->d, k->d, phi, ldphi, es)) return fail(GP_ERR_ARG, "phi overlaps X");
-  const PhiLayout L = phi_layout(k, n, r, p->n_poles);
+  const PhiLayout L = phi_layout(k, n, r, p->n_poles, p->precond_rank);
   if (n == 0) {  // nothing to solve: every column converged in 0 iterations
     phi_empty<<<1, 64, 0, stream>>>(r, status, iters);
     hipError_t e = hipGetLastError();

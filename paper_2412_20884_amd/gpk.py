@@ -64,7 +64,8 @@ class ImplicitParams(ctypes.Structure):
 
 class PhiParams(ctypes.Structure):
     _fields_ = [("n_poles", ctypes.c_int32), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("lambda_max", ctypes.c_double)]
+                ("lambda_max", ctypes.c_double), ("precond_rank", ctypes.c_int32),
+                ("precond_U", ctypes.c_void_p), ("precond_lam", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -547,8 +548,9 @@ def phi_workspace_size(kernel, params, n, r):
 
 
 def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit=2000,
-                lambda_max=None, out=None, ws=None, n_cheb=0):
+                lambda_max=None, out=None, ws=None, n_cheb=0, precond=None):
     """phi = A(theta)^{-1/2} xi through gp_phi_refresh.  xi may be 1-D (one column).
+    precond: (U, lam) from nystrom() to solve the shifted systems by preconditioned CG.
 
     Returns dict(phi, status, iters, bounds=(m, M))."""
     squeeze = xi.dim() == 1
@@ -561,7 +563,18 @@ def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit
     _same(dev, X.dtype, xi=xi2)
     _same(dev, torch.float64, theta=theta)
     k = make_kernel(kind, X, prec, n_cheb=n_cheb)
-    prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0))
+    rank, pU, plam = 0, None, None
+    if precond is not None:
+        U, lam = precond
+        _same(dev, X.dtype, precond_U=U)
+        _same(dev, torch.float64, precond_lam=lam)
+        if U.dim() != 2 or U.shape[0] != X.shape[0] or not U.is_contiguous():
+            raise ValueError(f"precond U must be a contiguous {X.shape[0]} x rank tensor")
+        _exact_len(lam, U.shape[1], "precond lam")
+        _on_gpu(U, lam)
+        rank, pU, plam = U.shape[1], _p(U), _p(lam)
+    prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0), int(rank), pU,
+                    plam)
     n, r = X.shape[0], xi2.shape[1]
     if xi2.shape[0] != n:
         raise ValueError(f"xi has {xi2.shape[0]} rows, X has {n}")

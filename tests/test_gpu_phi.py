@@ -181,3 +181,39 @@ def test_phi_identities_at_ard8_size():
     assert np.all(host(r1["status"]) == 0) and np.all(host(r2["status"]) == 0)
     assert gerr < 1e-4
     assert perr < 1e-3
+
+
+def _factor(X, th, kind, rank, dtype, seed):
+    om = to_dev(np.random.default_rng(seed).standard_normal((len(X), rank)), dtype)
+    return gpk.nystrom(to_dev(X, dtype), to_dev(th, torch.float64), om, kind)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n_poles", [15, 40])
+def test_phi_preconditioned_vs_oracle(dtype, n_poles):
+    """Nystrom-preconditioned shifted solves (the factor reused across the shifts, Section 3.1):
+    the same phi as the oracle's exact expansion, with fewer iterations than multi-shift CG; 40
+    poles take two batches of pole columns."""
+    X, th, xi = _problem("iso", 1400, 2, 131, 2, 1e-3)
+    X, xi = rounded(X, dtype), rounded(xi, dtype)
+    M = opoles.gershgorin_upper(X, th, "iso")
+    Xd, thd = to_dev(X, dtype), to_dev(th, torch.float64)
+    U, lam = _factor(X, th, "iso", 40, dtype, 132)
+    tol = 1e-13 if dtype == torch.float64 else 1e-6
+    plain = gpk.phi_refresh(Xd, thd, to_dev(xi, dtype), "iso", n_poles=n_poles, tol=tol,
+                            maxit=20000, lambda_max=M)
+    xin = to_dev(xi, dtype)
+    pre = gpk.phi_refresh(Xd, thd, xin, "iso", n_poles=n_poles, tol=tol, maxit=20000,
+                          lambda_max=M, precond=(U, lam), out=xin)  # in place
+    torch.cuda.synchronize()
+    assert np.all(host(pre["status"]) == 0) and np.all(host(plain["status"]) == 0)
+    it_plain, it_pre = host(plain["iters"]), host(pre["iters"])
+    print(f"iterations: multi-shift {it_plain}, preconditioned (largest pole) {it_pre}")
+    assert np.all(it_pre < 0.5 * it_plain)
+    ref = _oracle(X, th, "iso", xi, M, n_poles=n_poles)
+    m = np.exp(th[-1])
+    err = _col_err(host(pre["phi"]), ref)
+    bound = 1e-12 + 10 * (M / m) * 1e-13 if dtype == torch.float64 else 30 * (M / m) * EPS32
+    print(f"preconditioned phi error vs oracle {err:.2e} (bound {bound:.2e}), multi-shift "
+          f"{_col_err(host(plain['phi']), ref):.2e}")
+    assert err < bound
