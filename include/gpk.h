@@ -161,6 +161,8 @@ gp_status gp_kmatvec_noalloc(const gp_kernel *k, int64_t n, const void *X, const
  *   quad       device double[r], q_c = u_c^T A v_c (unweighted), or NULL
  *   AU, AV     device, n x r, leading dimensions ldau, ldav >= r, or NULL; A U is dQ/dv per
  *              column up to w_c, A V is dQ/du.  They must not overlap U or V or each other.
+ *              With U != V and both requested, r <= 16 runs as one pass of 2r columns
+ *              ([U | V] against [V | U], weights [w | 0]); larger r takes a second pass for A V.
  * At least one output must be non-NULL.
  */
 gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const double *theta,

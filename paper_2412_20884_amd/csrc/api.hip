@@ -27,9 +27,10 @@ gp_status hip_fail(hipError_t e, const char *where) {
   return fail(GP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-// Final fixed-order sum of the per-block records.  One thread per record entry.
+// Final fixed-order sum of the per-block records.  One thread per record entry; quad receives
+// the first nq column sums.
 __global__ void reduce_records(const double *rp, int64_t np, const double *rf, int64_t nf,
-                               int nrec, int nth, int L, double *grad, double *quad) {
+                               int nrec, int nth, int L, double *grad, double *quad, int nq) {
   const int e = threadIdx.x;
   if (e >= nrec) return;
   double s = 0.0;
@@ -38,8 +39,32 @@ __global__ void reduce_records(const double *rp, int64_t np, const double *rf, i
   if (e < nth) {
     const double f = (e >= 1 && e <= L) ? 2.0 * kLn2 : 1.0;
     if (grad) grad[e] = s * f;
-  } else if (quad) {
+  } else if (quad && e - nth < nq) {
     quad[e - nth] = s;
+  }
+}
+
+// Operands of the one-pass form of sum_c w_c u_c^T A v_c with both A U and A V (U != V):
+// Y = [U | V] and D = [V | U] (n x 2r), and the weights [w | 0].
+template <typename T>
+__global__ void pack_pair(int64_t n, int r, const T *U, int64_t ldu, const T *V, int64_t ldv,
+                          T *Y, T *D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * r) return;
+  const int64_t i = e / r;
+  const int c = (int)(e - i * r);
+  const T u = U[i * ldu + c], v = V[i * ldv + c];
+  Y[i * 2 * r + c] = u;
+  Y[i * 2 * r + r + c] = v;
+  D[i * 2 * r + c] = v;
+  D[i * 2 * r + r + c] = u;
+}
+
+__global__ void pack_weights(int r, const double *w, double *w2) {
+  const int c = threadIdx.x;
+  if (c < r) {
+    w2[c] = w ? w[c] : 1.0;
+    w2[r + c] = 0.0;
   }
 }
 
@@ -78,10 +103,11 @@ hipError_t launch_pass(const PassDesc &p, hipStream_t s) {
   return launch_pass_f32(p, s);
 }
 
-hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s) {
+hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s, int nq) {
   if (!grad && !quad) return hipSuccess;
   reduce_records<<<1, 128, 0, s>>>(p.rec_pair, pair_blocks(p), p.rec_fin, fin_blocks(p),
-                                   p.nrec, p.nth, p.kind == 0 ? 1 : p.d, grad, quad);
+                                   p.nrec, p.nth, p.kind == 0 ? 1 : p.d, grad, quad,
+                                   nq < 0 ? p.nrec - p.nth : nq);
   return hipGetLastError();
 }
 
@@ -210,6 +236,21 @@ static PassDesc base_desc(const gp_kernel *k, const Plan &pl, int64_t n, const d
   return p;
 }
 
+// gp_quadform_grad with U != V and both A U and A V for 2r <= kMaxRPass runs one pass of 2r
+// columns: its plan's workspace, then Y = [U | V], D = [V | U], the output [A U | A V] (n x 2r
+// each) and the weights [w | 0].
+static bool pair_pass(const gp_kernel *k, int r) { return k->kind != GP_SE_CHEB && 2 * r <= kMaxRPass; }
+
+static size_t pair_pack_offset(const gp_kernel *k, int64_t n, int r) {
+  return align256(make_plan(k, n, 2 * r, 1).L.total);
+}
+
+static size_t pair_pass_bytes(const gp_kernel *k, int64_t n, int r) {
+  if (!pair_pass(k, r)) return 0;
+  const size_t blk = align256(elem_size(k->prec) * (size_t)n * 2 * r);
+  return pair_pack_offset(k, n, r) + 3 * blk + align256(sizeof(double) * 2 * r);
+}
+
 void tune_force(const TuneCfg *c) {
   t_forced = c != nullptr;
   if (c) t_force_cfg = *c;
@@ -260,7 +301,9 @@ size_t gp_workspace_size(const gp_kernel *k, int64_t n, int32_t r) {
   if (check_kernel(k, true) != GP_OK || n < 0 || r < 0) return 0;
   if (n == 0 || r == 0) return 0;
   if (k->kind == GP_SE_CHEB) return cheb_workspace_size(k, n, r);
-  return make_plan(k, n, r, -1).L.total;
+  const size_t one = make_plan(k, n, r, -1).L.total;
+  const size_t pair = pair_pass_bytes(k, n, r);
+  return one > pair ? one : pair;
 }
 
 }  // extern "C"
@@ -366,14 +409,54 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
   if (k->kind == GP_SE_CHEB)
     return cheb_quadform_grad(k, n, X, theta, r, U, ldu, V, ldv, w, grad_theta, quad, AU, ldau,
                               AV, ldav, ws, ws_bytes, stream);
-  const Plan pl = make_plan(k, n, r, 1);
-  if (!ws || ws_bytes < pl.L.total)
-    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", pl.L.total,
+  const bool both = !sym && AU && AV && pair_pass(k, r);
+  const Plan pl = make_plan(k, n, both ? 2 * r : r, 1);
+  const size_t need = both ? pair_pass_bytes(k, n, r) : pl.L.total;
+  if (!ws || ws_bytes < need)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
                 ws ? ws_bytes : (size_t)0);
   char *wsp = (char *)ws;
   hipError_t e = launch_stage(k->prec == GP_F64 ? kF64 : kF32, X, n, k->d, pl.dp, k->kind,
                               theta, wsp, pl.L, stream);
   if (e != hipSuccess) return hip_fail(e, "stage");
+
+  if (both) {
+    // one pass of 2r columns: Y = P = [U | V], D = Q = [V | U], weights [w | 0]; then
+    // S_ij = sum_c w_c u_ic v_jc, q_c = v_c^T (A u_c) for c < r, the sigma^2 term
+    // sigma^2 sum_c w_c u_c . v_c, and the product [A U | A V]
+    const size_t blk = align256(es * (size_t)n * 2 * r);
+    char *Y2 = wsp + pair_pack_offset(k, n, r);
+    char *D2 = Y2 + blk, *O2 = D2 + blk;
+    double *w2 = (double *)(O2 + blk);
+    const unsigned eb = (unsigned)((n * r + 255) / 256);
+    if (k->prec == GP_F64)
+      pack_pair<double><<<eb, 256, 0, stream>>>(n, r, (const double *)U, ldu, (const double *)V,
+                                                ldv, (double *)Y2, (double *)D2);
+    else
+      pack_pair<float><<<eb, 256, 0, stream>>>(n, r, (const float *)U, ldu, (const float *)V, ldv,
+                                               (float *)Y2, (float *)D2);
+    pack_weights<<<1, 64, 0, stream>>>(r, w, w2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pack");
+    PassDesc p = base_desc(k, pl, n, theta, wsp);
+    p.R = 2 * r;
+    p.nrec = nth_of(k) + 2 * r;
+    p.P = p.Y = Y2;
+    p.Q = p.D = D2;
+    p.ldp = p.ldq = p.ldy = p.ldd = 2 * r;
+    p.w = w2;
+    p.out = O2;
+    p.ldo = 2 * r;
+    e = launch_pass(p, stream);
+    if (e != hipSuccess) return hip_fail(e, "quadform pass");
+    e = launch_reduce(p, grad_theta, quad, stream, r);
+    if (e != hipSuccess) return hip_fail(e, "reduce");
+    e = hipMemcpy2DAsync(AU, ldau * es, O2, 2 * r * es, r * es, n, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(AV, ldav * es, O2 + r * es, 2 * r * es, r * es, n,
+                           hipMemcpyDeviceToDevice, stream);
+    return e == hipSuccess ? GP_OK : hip_fail(e, "copy A U, A V");
+  }
 
   // Pass 1: gradient, q_c and one of the products.  Y is the operand whose product is wanted;
   // D is the other operand, so q_c = sum_i D_ic (A Y)_ic = u_c^T A v_c either way.
@@ -416,7 +499,7 @@ gp_status gp_quadform_grad(const gp_kernel *k, int64_t n, const void *X, const d
                          stream);
     if (e != hipSuccess) return hip_fail(e, "copy AU -> AV");
   } else if (!sym && AU && AV) {
-    // Pass 2: the second product without gradient sums.
+    // r > kMaxRPass / 2: pass 2, the second product without gradient sums.
     PassDesc q = base_desc(k, pl, n, theta, wsp);
     q.R = r;
     q.nrec = nth_of(k) + r;

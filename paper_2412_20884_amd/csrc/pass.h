@@ -61,7 +61,8 @@ int64_t fin_blocks(const PassDesc &p);
 hipError_t launch_stage(int prec, const void *X, int64_t n, int d, int dp, int kind,
                         const double *theta, char *ws, const WsLayout &L, hipStream_t s);
 hipError_t launch_pass(const PassDesc &p, hipStream_t s);
-hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s);
+// quad receives the first nq column sums (nq < 0: all of them).
+hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s, int nq = -1);
 
 bool mfma_supported(int prec, int kind, int d, int R);
 size_t mfma_scratch_bytes(int64_t n, int dp);

@@ -32,3 +32,10 @@ def col_rel_err(out, ref):
 def grad_rel_err(g, ref, scale):
     """max_p |g_p - ref_p| / scale_p, scale_p = sum_c |w_c| |u_c|^T |dA/dtheta_p| |v_c|."""
     return float(np.max(np.abs(g - ref) / np.maximum(scale, 1e-300)))
+
+
+def comp_rel_err(out, ref, absref):
+    """max_ic |out_ic - ref_ic| / (|A| |V|)_ic: the componentwise, condition-aware error (absref is
+    the oracle's product with |V|; every entry of A is positive, so |A| |V| = A |V|)."""
+    out = out.reshape(ref.shape)
+    return float(np.max(np.abs(out - ref) / np.maximum(absref, 1e-300)))

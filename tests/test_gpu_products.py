@@ -2,8 +2,9 @@
 
 Inputs are seeded and synthetic; the oracle sees the values the device holds (inputs rounded to
 the device precision and converted exactly to float64), so the measured error is the kernels'
-arithmetic error.  Tolerances: FP64 1e-11 relative; FP32 1e-5 relative (per column, 2-norm);
-gradients relative to the condition-aware scale sum_c |w_c| |u_c|^T |dA/dtheta| |v_c|.
+arithmetic error.  Tolerances: FP64 1e-11 relative; FP32 1e-5 relative, per column in the 2-norm
+and per entry against (|A| |V|)_ic (one wrong row cannot hide in a column norm); gradients
+relative to the condition-aware scale sum_c |w_c| |u_c|^T |dA/dtheta| |v_c|.
 Sizes span several 256-row blocks, ragged tails and the column-split path.
 """
 import numpy as np
@@ -12,7 +13,7 @@ import torch
 
 from oracle import gp as ogp
 from paper_2412_20884_amd import gpk, inputs as I
-from tests.gpu_util import DEV, col_rel_err, grad_rel_err, host, rounded, to_dev
+from tests.gpu_util import DEV, col_rel_err, comp_rel_err, grad_rel_err, host, rounded, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +38,7 @@ def test_kmatvec_small_fp64_workload(dtype):
     torch.cuda.synchronize()
     ref = ogp.matvec(X, w["theta"], "iso", V)
     assert col_rel_err(host(out), ref) < TOL[dtype]
+    assert comp_rel_err(host(out), ref, ogp.matvec(X, w["theta"], "iso", np.abs(V))) < TOL[dtype]
 
 
 @pytest.mark.parametrize("n", [1, 7, 300, 1000, 4099, 9001])
@@ -49,6 +51,7 @@ def test_kmatvec_iso_f32_sizes(n, r):
     torch.cuda.synchronize()
     ref = ogp.matvec(X, p["theta"], "iso", V)
     assert col_rel_err(host(out), ref) < TOL[torch.float32]
+    assert comp_rel_err(host(out), ref, ogp.matvec(X, p["theta"], "iso", np.abs(V))) < TOL[torch.float32]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -65,6 +68,9 @@ def test_kmatvec_ard_dims_shift_no_noise(dtype, d):
     ref_nn = ogp.matvec(X, p["theta"], "ard", V, no_noise=True)
     assert col_rel_err(host(out), ref) < TOL[dtype]
     assert col_rel_err(host(nn), ref_nn) < TOL[dtype]
+    absref = ogp.matvec(X, p["theta"], "ard", np.abs(V), col_shift=shift)
+    assert comp_rel_err(host(out), ref, absref) < TOL[dtype]
+    assert comp_rel_err(host(nn), ref_nn, ogp.matvec(X, p["theta"], "ard", np.abs(V), no_noise=True)) < TOL[dtype]
 
 
 def test_kmatvec_wide_r_and_strided_operands():
@@ -102,6 +108,7 @@ def test_quadform_symmetric(dtype, kind, d, n):
     assert np.max(np.abs(host(res["quad"]) - ref["quad"]) / qscale) < tol
     assert col_rel_err(host(res["AU"]), ref["AU"]) < tol
     assert col_rel_err(host(res["AV"]), ref["AV"]) < tol
+    assert comp_rel_err(host(res["AU"]), ref["AU"], ogp.matvec(X, th, kind, np.abs(U))) < tol
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -238,3 +245,25 @@ def test_autotuned_config_keeps_parity(kind, d, r):
     assert col_rel_err(host(res["AU"]), ref["AU"]) < 1e-5
     assert col_rel_err(host(out), ref["AU"]) < 1e-5
     assert grad_rel_err(host(res["grad"]), ref["grad"], _grad_scale(X, th, kind, U, U, np.ones(r))) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind,d,r", [("iso", 2, 16), ("ard", 5, 7), ("ard", 3, 17)])
+def test_quadform_unsymmetric_both_products(dtype, kind, d, r):
+    """U != V with A U and A V: one pass of 2r columns for r <= 16 (the matrix-core path at
+    2r >= 8 in float), two passes for r = 17; weights of both signs."""
+    p = _problem(kind, 2300, d, 97 + r, r)
+    X, U, V = (rounded(p[k], dtype) for k in ("X", "U", "V"))
+    th = p["theta"]
+    w = np.linspace(-1.0, 1.5, r)
+    res = gpk.quadform_grad(to_dev(X, dtype), to_dev(th, torch.float64), to_dev(U, dtype),
+                            to_dev(V, dtype), to_dev(w, torch.float64), kind, want_AU=True,
+                            want_AV=True)
+    torch.cuda.synchronize()
+    ref = ogp.quadform_grad(X, th, kind, U, V, w)
+    tol = TOL[dtype]
+    assert grad_rel_err(host(res["grad"]), ref["grad"], _grad_scale(X, th, kind, U, V, w)) < tol
+    qscale = np.diag(np.abs(U).T @ ogp.matvec(X, th, kind, np.abs(V)))
+    assert np.max(np.abs(host(res["quad"]) - ref["quad"]) / qscale) < tol
+    assert comp_rel_err(host(res["AU"]), ref["AU"], ogp.matvec(X, th, kind, np.abs(U))) < tol
+    assert comp_rel_err(host(res["AV"]), ref["AV"], ogp.matvec(X, th, kind, np.abs(V))) < tol
