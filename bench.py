@@ -182,12 +182,15 @@ def cpu_baseline(budget_s=15.0):
                       f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad"}
 
 
-def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
+def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0, rwm=True,
+                   precond_rank=128):
     """Chain-leapfrog-steps/s on the batched workload, batched (graph replay) vs plain.
 
     subset = k takes every k-th instance (k = 1: all 64 instances). group = g > 0 runs the
     batched modes as consecutive persistent launches over g instances each (all chains of
     those instances), with a progress line per launch; 0 runs every instance in one launch.
+    Mode graph_nystrom is graph mode with every solve preconditioned by a rank-`precond_rank`
+    Nystrom factor per instance, built once at the instance's theta_0 (timed separately).
     rwm = False leaves out the random-walk Metropolis leg.
     """
     import torch
@@ -232,13 +235,32 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
     u = torch.tensor(np.concatenate([b["u"] for b in inst]), dtype=torch.float64, device=dev)
     out = {}
     ref_theta = None
+    U_all = lam_all = None
+    if "graph_nystrom" in modes:
+        Us, lams = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for bi, b in enumerate(inst):
+            Xb = X[xoffs[bi]:xoffs[bi] + ns[bi] * ds[bi]].view(ns[bi], ds[bi])
+            om = torch.tensor(inputs.rng(1000 + bi, inputs.P_V).standard_normal((ns[bi], precond_rank)),
+                              dtype=torch.float32, device=dev)
+            U, lam = gpk.nystrom(Xb, torch.tensor(b["theta"], dtype=torch.float64, device=dev), om, "ard")
+            Us.append(U)
+            lams.append(lam)
+        U_all, lam_all = torch.cat(Us).contiguous(), torch.cat(lams).contiguous()
+        torch.cuda.synchronize()
+        out["nystrom_build"] = {"rank": precond_rank, "seconds": time.perf_counter() - t0,
+                                "instances": len(inst)}
+        del Us
     for mode in modes:
-        m = {"plain": gpk.PLAIN, "batched": gpk.BATCHED, "graph": gpk.GRAPH}[mode]
+        m = {"plain": gpk.PLAIN, "batched": gpk.BATCHED, "graph": gpk.GRAPH,
+             "graph_nystrom": gpk.GRAPH}[mode]
         th = torch.tensor(th0, dtype=torch.float64, device=dev)
         pi = torch.tensor(pi0, dtype=torch.float64, device=dev)
         x = torch.zeros(sum(ns) * C, dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
         kw = dict(n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=1e-6, cg_maxit=2000, mode=m)
+        pre = mode == "graph_nystrom"
         if mode == "plain":
             # one instance per call so progress is visible; the library runs chains one at a time
             t = 0.0
@@ -275,11 +297,12 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
                 r0, r1 = offs[gi[0]], offs[gi[-1]] + ns[gi[-1]]
                 x0_, x1_ = xoffs[gi[0]], xoffs[gi[-1]] + ns[gi[-1]] * ds[gi[-1]]
                 t0 = time.perf_counter()
+                pg = (U_all[r0:r1], lam_all[gi[0] * precond_rank:(gi[-1] + 1) * precond_rank]) if pre else None
                 r = gpk.hmc_leapfrog(X[x0_:x1_], y[r0:r1], phi[C * r0:C * r1], th[toff:toff + nth_g],
                                      pi[toff:toff + nth_g], x[C * r0:C * r1], "ard", [ns[b] for b in gi],
                                      [offs[b] - r0 for b in gi], C, d=[ds[b] for b in gi],
                                      x_offsets=[xoffs[b] - x0_ for b in gi], u=u[gi[0] * C:(gi[-1] + 1) * C],
-                                     **kw)
+                                     precond=pg, **kw)
                 torch.cuda.synchronize()
                 t += time.perf_counter() - t0
                 sts.append(r["status"].cpu().numpy())
@@ -292,7 +315,8 @@ def bench_leapfrog(modes=("graph", "plain"), subset=8, group=0, rwm=True):
             acc = np.concatenate(accs)
         else:
             t0 = time.perf_counter()
-            res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u, **kw)
+            res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u,
+                                   precond=(U_all, lam_all) if pre else None, **kw)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             st = res["status"].cpu().numpy()
@@ -523,12 +547,13 @@ def bench_small_fp64(tol=1e-6):
     return out
 
 
-def bench_cheb2d(tol=1e-6):
+def bench_cheb2d(tol=1e-6, rank=500, refresh_every=5):
     """The Section 4.3 stand-in (N = 3000, d = 2, Chebyshev-amplitude kernel, N_cheb = 4, B = 10
     chains, N_int = 3 leapfrog steps of 0.03, FP64): each HMC update refreshes phi for every chain
-    at its current theta on the device, then runs the 10 chains' trajectories in one plain-mode
-    call.  The paper's run of this shape also rebuilt a Nystrom preconditioner every five updates;
-    here CG is unpreconditioned."""
+    at its current theta on the device, then runs the 10 chains' trajectories in one graph-mode
+    call (persistent launch replayed).  Run twice: with plain CG, and with the paper's rank-500
+    Nystrom preconditioner rebuilt every five updates (at chain 0's theta, shared by the chains)
+    and used by both the trajectory solves and the phi refresh."""
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
@@ -539,46 +564,68 @@ def bench_cheb2d(tol=1e-6):
     nt = wl["theta"].size
     X = torch.tensor(wl["X"], dtype=torch.float64, device=dev)
     y = torch.tensor(wl["y"], dtype=torch.float64, device=dev)
-    th = torch.tensor(np.tile(wl["theta"], C), dtype=torch.float64, device=dev)
-    x = torch.zeros(n * C, dtype=torch.float64, device=dev)
-    phi = torch.empty(n * C, dtype=torch.float64, device=dev)
     xi = torch.tensor(wl["xi"], dtype=torch.float64, device=dev)
-    acc, cg, ph_it, dH, t_phi = 0, 0, 0, [], 0.0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(nu):
-        t1 = time.perf_counter()
-        for c in range(C):
-            r = gpk.phi_refresh(X, th[c * nt:(c + 1) * nt], xi[k, c], "cheb", tol=tol, maxit=3000,
-                                n_cheb=nc)
-            phi[c * n:(c + 1) * n] = r["phi"].reshape(-1)
-            ph_it += int(r["iters"][0])
-            if int(r["status"][0]) != 0:
-                raise RuntimeError(f"cheb2d: phi refresh of chain {c} failed at update {k}")
+    omega = torch.tensor(inputs.rng(inputs.WORKLOAD_SEEDS["cheb2d"], inputs.P_V).standard_normal((n, rank)),
+                         dtype=torch.float64, device=dev)
+
+    def run(use_precond):
+        th = torch.tensor(np.tile(wl["theta"], C), dtype=torch.float64, device=dev)
+        x = torch.zeros(n * C, dtype=torch.float64, device=dev)
+        phi = torch.empty(n * C, dtype=torch.float64, device=dev)
+        pi = torch.empty(C * nt, dtype=torch.float64, device=dev)
+        u = torch.empty(C, dtype=torch.float64, device=dev)
+        acc, cg, ph_it, dH, t_phi, t_nys = 0, 0, 0, [], 0.0, 0.0
+        pre, res = None, None
         torch.cuda.synchronize()
-        t_phi += time.perf_counter() - t1
-        pi = torch.tensor(wl["pi"][k].ravel(), dtype=torch.float64, device=dev)
-        u = torch.tensor(wl["u"][k], dtype=torch.float64, device=dev)
-        r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi, th, pi, x, "cheb", [n], [0], C, d=[2], u=u,
-                             n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=tol, cg_maxit=3000,
-                             mode=gpk.PLAIN, n_cheb=nc)
-        torch.cuda.synchronize()
-        st = r["status"].cpu().numpy()
-        if np.any(st != 0):
-            raise RuntimeError(f"cheb2d: trajectory status {st.tolist()} at update {k}")
-        acc += int(r["accepted"].sum())
-        cg += int(r["cg_iters"].sum())
-        dH += (r["H1"] - r["H0"]).cpu().numpy().tolist()
-    t = time.perf_counter() - t0
-    steps = nu * C * wl["n_steps"]
+        t0 = time.perf_counter()
+        for k in range(nu):
+            if use_precond and k % refresh_every == 0:
+                t1 = time.perf_counter()
+                U, lam = gpk.nystrom(X, th[:nt], omega, "cheb", n_cheb=nc)
+                pre = (U, lam)
+                torch.cuda.synchronize()
+                t_nys += time.perf_counter() - t1
+            t1 = time.perf_counter()
+            for c in range(C):
+                r = gpk.phi_refresh(X, th[c * nt:(c + 1) * nt], xi[k, c], "cheb", tol=tol, maxit=3000,
+                                    n_cheb=nc, precond=pre)
+                phi[c * n:(c + 1) * n] = r["phi"].reshape(-1)
+                ph_it += int(r["iters"][0])
+                if int(r["status"][0]) != 0:
+                    raise RuntimeError(f"cheb2d: phi refresh of chain {c} failed at update {k}")
+            torch.cuda.synchronize()
+            t_phi += time.perf_counter() - t1
+            pi.copy_(torch.from_numpy(wl["pi"][k].ravel()))
+            u.copy_(torch.from_numpy(wl["u"][k]))
+            res = gpk.hmc_leapfrog(X.view(-1, 1), y, phi, th, pi, x, "cheb", [n], [0], C, d=[2], u=u,
+                                   n_steps=wl["n_steps"], dt=wl["dt"], cg_tol=tol, cg_maxit=3000,
+                                   mode=gpk.GRAPH, n_cheb=nc, precond=pre, outputs=res)
+            torch.cuda.synchronize()
+            st = res["status"].cpu().numpy()
+            if np.any(st != 0):
+                raise RuntimeError(f"cheb2d: trajectory status {st.tolist()} at update {k}")
+            acc += int(res["accepted"].sum())
+            cg += int(res["cg_iters"].sum())
+            dH += (res["H1"] - res["H0"]).cpu().numpy().tolist()
+        t = time.perf_counter() - t0
+        steps = nu * C * wl["n_steps"]
+        return {"chain_leapfrog_steps_per_s": steps / t, "seconds": t, "phi_refresh_seconds": t_phi,
+                "nystrom_build_seconds": t_nys, "updates_per_s": nu * C / t,
+                "accept_rate": acc / (nu * C),
+                "mean_cg_iters_per_solve": cg / (nu * C * (wl["n_steps"] + 2)),
+                "mean_phi_iters": ph_it / (nu * C), "max_abs_dH": float(np.max(np.abs(dH))),
+                "theta_final": th.cpu().numpy()}
+
+    plain = run(False)
+    prec = run(True)
+    dtheta = float(np.max(np.abs(plain.pop("theta_final") - prec.pop("theta_final"))))
     out = {"workload": f"cheb2d: N={n}, d=2 (half uniform on [-1,1]^2, half in 8 clusters), "
                        f"Chebyshev-amplitude SE, N_cheb={nc} ({nt} hyperparameters), FP64, {C} chains, "
                        f"{nu} updates of {wl['n_steps']} leapfrog steps of dt {wl['dt']:g}, CG tol {tol:g}, "
-                       "phi refreshed per chain and update on the device",
-           "chain_leapfrog_steps_per_s": steps / t, "seconds": t, "phi_refresh_seconds": t_phi,
-           "updates_per_s": nu * C / t, "accept_rate": acc / (nu * C),
-           "mean_cg_iters_per_solve": cg / (nu * C * (wl["n_steps"] + 2)),
-           "mean_phi_iters": ph_it / (nu * C), "max_abs_dH": float(np.max(np.abs(dH)))}
+                       "phi refreshed per chain and update on the device, trajectories in graph mode",
+           "graph_plain_cg": plain,
+           f"graph_nystrom_rank{rank}_every{refresh_every}": prec,
+           "max_abs_theta_diff_between_the_two": dtheta}
     log(f"cheb2d: {out}")
     return out
 
@@ -656,7 +703,8 @@ def main():
     ap.add_argument("--no-leapfrog", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--leapfrog-modes", default="graph,plain")
+    ap.add_argument("--leapfrog-modes", default="graph,graph_nystrom,plain")
+    ap.add_argument("--leapfrog-precond-rank", type=int, default=128)
     ap.add_argument("--leapfrog-subset", type=int, default=16)
     ap.add_argument("--leapfrog-group", type=int, default=0,
                     help="instances per persistent launch in the batched modes (0: all in one)")
@@ -723,7 +771,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     if not args.no_leapfrog:
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset,
-                                          args.leapfrog_group, not args.no_rwm)
+                                          args.leapfrog_group, not args.no_rwm,
+                                          args.leapfrog_precond_rank)
     if not args.no_ard64:
         line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt)
     if not args.no_precond:

@@ -8,11 +8,13 @@
 namespace gpk {
 
 // Jobs a chain can publish; every job is split into n_rb row blocks x n_cs column splits.
-enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3 };
+enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3, kJobZ = 4 };
 // Why the current solve + quadratic-form pass is being done.
 enum HmcCtxKind { kCtxEnergy0 = 0, kCtxForce = 1, kCtxEnergy1 = 2 };
 
-constexpr int kHmcRec = 72;        // doubles per tile record: [0..7] scalars, [8 + k] gradient
+// doubles per tile record: [0..7] scalars, [8 + k] length-scale gradient; the Chebyshev-amplitude
+// kernel adds its N_cheb^d <= 64 coefficient sums at [9 + m]
+constexpr int kHmcRec = 80;
 constexpr int kHmcTile = 256;      // rows per tile (one per thread)
 constexpr int kHmcMaxTheta = kMaxD + 2;
 constexpr int kHmcMaxRank = 512;   // largest Nystrom rank of the preconditioned solves
@@ -35,14 +37,20 @@ struct HmcChain {
   T *xs;       // n x dp scaled coordinates
   T *r, *p, *q, *x0;
   T *Z;        // n x 2: [x | phi]
+  T *lc;       // GP_SE_CHEB: log2 of the amplitude e^{C(x_i)} at the current theta (n)
+  int ncheb;   // GP_SE_CHEB: N_cheb
   double *qpart;  // n_cs x n partial products (n_cs > 1 only)
   double *rec;    // n_jobs x kHmcRec
   double theta0[kHmcMaxTheta], pi0[kHmcMaxTheta], F[kHmcMaxTheta];
   double minv[kHmcMaxTheta];  // diagonal of the inverse mass matrix
-  // Nystrom preconditioner of the solves (prank = 0: plain CG): U n x prank, lam prank
+  // Nystrom preconditioner of the solves (prank = 0: plain CG): U n x prank, lam prank; in the
+  // workspace the row blocks' partial sums of U^T w1, U^T w2 [n_rb][2][prank], g = U^T r and
+  // h = c o g [prank]
   const T *pU;
   const double *plam;
   int prank;
+  int zfirst;     // the pending z job starts a solve (p = z) rather than continuing it
+  double *pgp, *pg, *ph;
   double centre[kMaxD];
   // schedule
   int n_rb, n_cs, n_jobs;

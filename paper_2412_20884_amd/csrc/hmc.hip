@@ -20,16 +20,16 @@ gp_status hip_fail(hipError_t e, const char *where);
 
 hipError_t hmc_kickoff_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
 hipError_t hmc_kickoff_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
-hipError_t hmc_tiles_f32(void *, int, int, hipStream_t);
-hipError_t hmc_tiles_f64(void *, int, int, hipStream_t);
+hipError_t hmc_tiles_f32(void *, int, int, int, int, hipStream_t);
+hipError_t hmc_tiles_f64(void *, int, int, int, int, hipStream_t);
 hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, int, hipStream_t);
 hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, int, hipStream_t);
-hipError_t hmc_gather_f32(void *, int, hipStream_t);
-hipError_t hmc_gather_f64(void *, int, hipStream_t);
+hipError_t hmc_gather_f32(void *, int, int, hipStream_t);
+hipError_t hmc_gather_f64(void *, int, int, hipStream_t);
 hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, hipStream_t);
+                              int, int, int, hipStream_t);
 hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, hipStream_t);
+                              int, int, int, hipStream_t);
 hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
 hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
 hipError_t hmc_check_f32(void *, int, hipStream_t);
@@ -55,8 +55,11 @@ struct ChainLayout {
 size_t chain_bytes(int prec) { return prec == GP_F64 ? sizeof(HmcChain<double>) : sizeof(HmcChain<float>); }
 
 // Chains whose jobs run through the product entry points (gp_kmatvec / gp_quadform_grad) rather
-// than the persistent tile kernels: the bfloat16 cross term and the Chebyshev-amplitude kernel.
-bool uses_ext(int prec, int kind) { return prec == GP_BF16X || kind == GP_SE_CHEB; }
+// than the tile kernels: the bfloat16 cross term.
+bool uses_ext(int prec, int kind) {
+  (void)kind;
+  return prec == GP_BF16X;
+}
 
 constexpr int kPlainCheck = 4;  // plain mode: jobs between host checks of a tile chain
 
@@ -68,7 +71,7 @@ int plain_splits(int64_t n) {
   return (int)std::max<int64_t>(1, s);
 }
 
-size_t region_bytes(const InstInfo &in, int prec, int n_cs) {
+size_t region_bytes(const InstInfo &in, int prec, int n_cs, int prank) {
   const size_t es = prec == GP_F64 ? 8 : 4;
   const int64_t n = in.n;
   const int n_rb = (int)((n + kHmcTile - 1) / kHmcTile);
@@ -76,13 +79,15 @@ size_t region_bytes(const InstInfo &in, int prec, int n_cs) {
   o += align256(es * n * in.dp);     // xs
   o += 4 * align256(es * n);         // r, p, q, x0
   o += align256(es * 2 * n);         // Z
+  o += align256(es * n);             // lc (Chebyshev-amplitude log2 amplitudes)
   if (n_cs > 1) o += align256(sizeof(double) * n_cs * n);
   o += align256(sizeof(double) * (size_t)n_rb * n_cs * kHmcRec);
+  if (prank > 0) o += align256(sizeof(double) * (size_t)(2 * n_rb + 2) * prank);  // pgp, pg, ph
   return o;
 }
 
 ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode,
-                        int kind, int n_cheb) {
+                        int kind, int n_cheb, int prank) {
   ChainLayout L;
   const int nc = (int)inst.size() * chains;
   size_t o = 0;
@@ -103,7 +108,7 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
       L.per_chain.push_back(o);
       L.n_rb.push_back(n_rb);
       L.n_cs.push_back(n_cs);
-      o += region_bytes(in, prec, n_cs);
+      o += region_bytes(in, prec, n_cs, prank);
     }
   }
   L.prod = o;
@@ -141,7 +146,9 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   if (p->mode != GP_HMC_PLAIN && p->mode != GP_HMC_BATCHED && p->mode != GP_HMC_GRAPH)
     return fail(GP_ERR_ARG, "unknown mode %d", p->mode);
   if (uses_ext(k->prec, k->kind) && p->mode != GP_HMC_PLAIN)
-    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X and GP_SE_CHEB trajectories run in GP_HMC_PLAIN mode");
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories run in GP_HMC_PLAIN mode");
+  if (uses_ext(k->prec, k->kind) && p->precond_rank > 0)
+    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories take no preconditioner");
   if (!b) return fail(GP_ERR_ARG, "batch is NULL");
   if (b->n_inst < 1 || b->chains_per_inst < 1)
     return fail(GP_ERR_SHAPE, "n_inst and chains_per_inst must be >= 1");
@@ -201,7 +208,8 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
 }
 
 template <typename T>
-void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const ChainLayout &L,
+void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int chains,
+                 const ChainLayout &L,
                  char *ws, const gp_hmc_params *p,
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
@@ -252,6 +260,9 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const 
       r += 4 * vb;
       ch.Z = (T *)r;
       r += align256(es * 2 * n);
+      ch.lc = (T *)r;
+      r += align256(es * n);
+      ch.ncheb = kind == GP_SE_CHEB ? n_cheb : 0;
       ch.n_rb = L.n_rb[c];
       ch.n_cs = L.n_cs[c];
       ch.n_jobs = ch.n_rb * ch.n_cs;
@@ -261,6 +272,12 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int chains, const 
         r += align256(sizeof(double) * ch.n_cs * n);
       }
       ch.rec = (double *)r;
+      r += align256(sizeof(double) * (size_t)ch.n_jobs * kHmcRec);
+      if (ch.prank > 0) {
+        ch.pgp = (double *)r;
+        ch.pg = ch.pgp + (size_t)2 * ch.n_rb * ch.prank;
+        ch.ph = ch.pg + ch.prank;
+      }
       ch.ext = ext;
     }
     tofs += in.nth;
@@ -303,7 +320,8 @@ extern "C" {
 size_t gp_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b) {
   std::vector<InstInfo> inst;
   if (collect(k, p, b, inst) != GP_OK) return 0;
-  return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind, k->n_cheb).total;
+  return make_layout(inst, b->chains_per_inst, k->prec, p->mode, k->kind, k->n_cheb,
+                     p->precond_rank).total;
 }
 
 // One trajectory (rwm = 0) or one random-walk Metropolis update (rwm = 1) of every chain.
@@ -318,7 +336,8 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status)
     return fail(GP_ERR_ARG, "X, y, phi, theta, pi, x_warm, H0, H1, accepted and status must be non-NULL");
   const int chains = b->chains_per_inst;
-  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind, k->n_cheb);
+  const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind, k->n_cheb,
+                                    p->precond_rank);
   if (!ws || ws_bytes < L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -328,12 +347,12 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   std::vector<char> desc;
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
-    fill_chains<double>(inst, k->kind, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+    fill_chains<double>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
                         accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
-    fill_chains<float>(inst, k->kind, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
+    fill_chains<float>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
                        accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
@@ -373,7 +392,9 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   prm.dt = p->dt;
   prm.tol2 = p->cg_tol * p->cg_tol;
   prm.cg_maxit = p->cg_maxit;
-  prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (p->cg_maxit + 2) + 4,
+  // a preconditioned CG iteration is two jobs (the product and the z job)
+  const int64_t per_it = p->precond_rank > 0 ? 2 : 1;
+  prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 3) + 4,
                                         (int64_t)1 << 30);
   prm.rwm = rwm;
   HmcQueue qu;
@@ -385,6 +406,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   void *chains_dev = w + L.chains;
   const bool f64 = k->prec == GP_F64;
   const int pc = p->precond_rank > 0 ? 1 : 0;
+  const int ch = k->kind == GP_SE_CHEB ? 1 : 0;
   const size_t cb = chain_bytes(k->prec);
 
   constexpr int kJobToDone = 6;
@@ -425,11 +447,13 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
                                                     L.prod_bytes, stream);
           if (ps != GP_OK) return ps;
         } else {
-          e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, stream) : hmc_tiles_f32(cp, n_jobs, dpc, stream);
+          e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, ch, pc, stream)
+                  : hmc_tiles_f32(cp, n_jobs, dpc, ch, pc, stream);
           // with column splits the product is gathered by a multi-workgroup pass before the
           // (single-workgroup) epilogue
           if (e == hipSuccess && L.n_cs[c] > 1)
-            e = f64 ? hmc_gather_f64(cp, L.n_rb[c], stream) : hmc_gather_f32(cp, L.n_rb[c], stream);
+            e = f64 ? hmc_gather_f64(cp, L.n_rb[c], pc, stream)
+                    : hmc_gather_f32(cp, L.n_rb[c], pc, stream);
         }
         if (e == hipSuccess)
           e = f64 ? hmc_epilogue_f64(cp, prm, pc, stream) : hmc_epilogue_f32(cp, prm, pc, stream);
@@ -458,8 +482,8 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
             : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, s)
-            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, s);
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, s)
+            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, s);
     if (r != hipSuccess) return r;
     return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
   };
@@ -475,6 +499,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   key.insert(key.end(), (const char *)&grid, (const char *)(&grid + 1));
   key.insert(key.end(), (const char *)&dpmax, (const char *)(&dpmax + 1));
   key.insert(key.end(), (const char *)&pc, (const char *)(&pc + 1));
+  key.insert(key.end(), (const char *)&ch, (const char *)(&ch + 1));
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {
     if (ge.exec) {

@@ -146,7 +146,8 @@ def test_cheb_phi_refresh():
     assert col_rel_err(host(res["phi"]), ref) < 1e-9
 
 
-def test_cheb_plain_trajectory_fp64():
+@pytest.mark.parametrize("mode", [gpk.PLAIN, gpk.BATCHED, gpk.GRAPH])
+def test_cheb_trajectory_fp64(mode):
     """The paper's verification setting (Section 4.1) scaled up: d = 1, N_cheb = 2, 2 l^2 = 1,
     sigma^2 = 0.1, here with N = 200 points on [-1, 1) and y = cos(3 x); 6 leapfrog steps."""
     n = 200
@@ -162,7 +163,7 @@ def test_cheb_plain_trajectory_fp64():
     xd = torch.zeros(n, dtype=torch.float64, device="cuda:0")
     r = gpk.hmc_leapfrog(to_dev(X, torch.float64).reshape(-1, 1), to_dev(y, torch.float64),
                          to_dev(phi, torch.float64), thd, pid, xd, "cheb", [n], [0], 1, d=[1],
-                         n_steps=6, dt=0.05, cg_tol=1e-12, cg_maxit=2000, mode=gpk.PLAIN, n_cheb=2)
+                         n_steps=6, dt=0.05, cg_tol=1e-12, cg_maxit=2000, mode=mode, n_cheb=2)
     torch.cuda.synchronize()
     th1, pi1 = ohmc.leapfrog(X, "cheb", y, phi, th, pi0, 0.05, 6)
     assert int(r["status"][0]) == 0
@@ -170,10 +171,67 @@ def test_cheb_plain_trajectory_fp64():
     assert np.max(np.abs(host(pid) - pi1)) < 1e-8
     H1 = ohmc.hamiltonian(X, th1, "cheb", y, phi, pi1)
     assert abs(float(r["H1"][0]) - H1) < 1e-8 * abs(H1)
-    with pytest.raises(gpk.GpkError):
-        gpk.hmc_leapfrog(to_dev(X, torch.float64).reshape(-1, 1), to_dev(y, torch.float64),
-                         to_dev(phi, torch.float64), thd, pid, xd, "cheb", [n], [0], 1, d=[1],
-                         n_steps=2, dt=0.05, mode=gpk.BATCHED, n_cheb=2)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_cheb_batched_chains_match_oracle_and_graph(dtype):
+    """Six chains at different theta (d = 2, N_cheb = 3, N = 700, and a second instance with d = 3,
+    N_cheb = 2, N = 400), 4 leapfrog steps: the persistent launch and its graph replay agree bit for
+    bit, every chain follows the oracle's leapfrog (FP64 1e-8; float32 2e-4), and the plain form
+    takes the same decisions."""
+    C = 3
+    specs = [(700, 2, 3, 41), (400, 3, 2, 42)]
+    insts = []
+    for n, d, nc, seed in specs:
+        X, th, _, _ = _problem(n, d, nc, seed)
+        X = rounded(X, dtype)
+        y = rounded(np.sin(3.0 * X[:, 0]) + 0.3 * X[:, -1], dtype)
+        g = np.random.default_rng([seed, 7])
+        ths = [th + 0.03 * g.standard_normal(th.size) for _ in range(C)]
+        phis = [rounded(np.linalg.solve(np.linalg.cholesky(ogp.a_matrix(X, t, "cheb")).T,
+                                        g.standard_normal(n)), dtype) for t in ths]
+        pis = [0.5 * g.standard_normal(th.size) for _ in range(C)]
+        insts.append(dict(X=X, y=y, ths=ths, phis=phis, pis=pis, n=n, d=d, nc=nc))
+    # both instances share N_cheb only if equal: run them as two batches of C chains each
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    for b in insts:
+        n, d, nc = b["n"], b["d"], b["nc"]
+        u = np.random.default_rng(n).uniform(size=C)
+        out = {}
+        for mode in (gpk.GRAPH, gpk.BATCHED, gpk.PLAIN):
+            thd = to_dev(np.concatenate(b["ths"]), torch.float64)
+            pid = to_dev(np.concatenate(b["pis"]), torch.float64)
+            xd = torch.zeros(n * C, dtype=dtype, device="cuda:0")
+            r = gpk.hmc_leapfrog(to_dev(b["X"], dtype).reshape(-1, 1), to_dev(b["y"], dtype),
+                                 to_dev(np.concatenate(b["phis"]), dtype), thd, pid, xd, "cheb",
+                                 [n], [0], C, d=[d], u=to_dev(u, torch.float64), n_steps=4,
+                                 dt=0.03, cg_tol=tol, cg_maxit=4000, mode=mode, n_cheb=nc)
+            torch.cuda.synchronize()
+            out[mode] = {"theta": host(thd), "pi": host(pid), "H0": host(r["H0"]),
+                         "H1": host(r["H1"]), "accepted": r["accepted"].cpu().numpy(),
+                         "status": r["status"].cpu().numpy()}
+        for key in out[gpk.GRAPH]:
+            np.testing.assert_array_equal(out[gpk.GRAPH][key], out[gpk.BATCHED][key], err_msg=key)
+        np.testing.assert_array_equal(out[gpk.GRAPH]["accepted"], out[gpk.PLAIN]["accepted"])
+        assert np.all(out[gpk.GRAPH]["status"] == 0)
+        nt = nc ** d + 2
+        # float32: solves to a 1e-6 recurrence residual at condition ~1e3 give ~1e-4 in theta
+        bound = 1e-8 if dtype == torch.float64 else 1e-3
+        for c in range(C):
+            th1, pi1 = ohmc.leapfrog(b["X"], "cheb", b["y"], b["phis"][c], b["ths"][c], b["pis"][c],
+                                     0.03, 4)
+            H0 = ohmc.hamiltonian(b["X"], b["ths"][c], "cheb", b["y"], b["phis"][c], b["pis"][c])
+            H1 = ohmc.hamiltonian(b["X"], th1, "cheb", b["y"], b["phis"][c], pi1)
+            o = out[gpk.GRAPH]
+            htol = 1e-8 if dtype == torch.float64 else 1e-4
+            assert abs(o["H0"][c] - H0) < htol * max(1.0, abs(H0))
+            assert abs(o["H1"][c] - H1) < htol * max(1.0, abs(H1))
+            got = o["theta"][c * nt:(c + 1) * nt]
+            if o["accepted"][c]:
+                print(f"chain {c}: |theta - oracle| {np.max(np.abs(got - th1)):.2e}")
+                assert np.max(np.abs(got - th1)) < bound, (c, got - th1)
+            else:
+                np.testing.assert_array_equal(got, b["ths"][c])
 
 
 def test_cheb_autograd_gradcheck():
