@@ -314,9 +314,21 @@ def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0,
             its = np.concatenate(itl)
             acc = np.concatenate(accs)
         else:
+            # one launch for every chain; the scheduler's progress word (pinned host memory) is
+            # read while it runs, so that a long launch prints progress
+            prog = torch.zeros(1, dtype=torch.int32).pin_memory()
             t0 = time.perf_counter()
             res = gpk.hmc_leapfrog(X, y, phi, th, pi, x, "ard", ns, offs, C, d=ds, x_offsets=xoffs, u=u,
-                                   precond=(U_all, lam_all) if pre else None, **kw)
+                                   precond=(U_all, lam_all) if pre else None,
+                                   progress=prog if m != gpk.PLAIN else None, **kw)
+            done_ev = torch.cuda.Event()
+            done_ev.record()
+            last = t0
+            while not done_ev.query():
+                time.sleep(0.002)
+                if time.perf_counter() - last > 20.0:
+                    last = time.perf_counter()
+                    log(f"  {mode}: {int(prog[0])} of {len(ns) * C} chains finished, {last - t0:.0f} s")
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             st = res["status"].cpu().numpy()
@@ -705,6 +717,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--leapfrog-modes", default="graph,graph_nystrom,plain")
     ap.add_argument("--leapfrog-precond-rank", type=int, default=128)
+    ap.add_argument("--no-leapfrog-full", action="store_true",
+                    help="leave out the one-launch run of all 64 batched instances (~2.5 min)")
     ap.add_argument("--leapfrog-subset", type=int, default=16)
     ap.add_argument("--leapfrog-group", type=int, default=0,
                     help="instances per persistent launch in the batched modes (0: all in one)")
@@ -773,6 +787,11 @@ def main():
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset,
                                           args.leapfrog_group, not args.no_rwm,
                                           args.leapfrog_precond_rank)
+    if not args.no_leapfrog_full:
+        # the whole batched workload (64 instances x 8 chains, 20 steps) in one persistent launch,
+        # Nystrom-preconditioned, graph-replayed
+        line["leapfrog_full"] = bench_leapfrog(("graph_nystrom",), 1, 0, False,
+                                               args.leapfrog_precond_rank)
     if not args.no_ard64:
         line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt)
     if not args.no_precond:

@@ -219,6 +219,9 @@ typedef struct {
   int32_t precond_rank;      /* 0..512; rank <= n_b for every instance */
   const void *precond_U;     /* device, packed per instance, or NULL when precond_rank = 0 */
   const double *precond_lam; /* device, packed per instance, or NULL when precond_rank = 0 */
+  int32_t *progress;  /* host-pinned (hipHostMalloc) or device int32, or NULL: in the batched and
+                         graph modes, the number of chains finished so far, stored as chains finish
+                         (a long launch can be watched from the host) */
 } gp_hmc_params;
 
 enum {

@@ -89,6 +89,7 @@ struct HmcQueue {
   unsigned int *chains_done;
   unsigned int *abort;
   unsigned int *order;       // chain indices, largest problems first
+  int *progress;             // caller's progress word (finished chains), or null
 };
 
 }  // namespace gpk

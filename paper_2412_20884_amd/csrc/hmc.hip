@@ -403,6 +403,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   qu.chains_done = (unsigned *)(w + L.hdr_cnt);
   qu.abort = (unsigned *)(w + L.hdr_cnt + 4);
   qu.order = (unsigned *)(w + L.hdr_order);
+  qu.progress = p->progress;
   void *chains_dev = w + L.chains;
   const bool f64 = k->prec == GP_F64;
   const int pc = p->precond_rank > 0 ? 1 : 0;
@@ -500,6 +501,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   key.insert(key.end(), (const char *)&dpmax, (const char *)(&dpmax + 1));
   key.insert(key.end(), (const char *)&pc, (const char *)(&pc + 1));
   key.insert(key.end(), (const char *)&ch, (const char *)(&ch + 1));
+  key.insert(key.end(), (const char *)&qu.progress, (const char *)(&qu.progress + 1));
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {
     if (ge.exec) {

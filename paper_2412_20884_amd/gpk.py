@@ -47,7 +47,8 @@ class HmcParams(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int32), ("dt", ctypes.c_double), ("cg_tol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("inv_mass", ctypes.POINTER(ctypes.c_double)), ("precond_rank", ctypes.c_int32),
-                ("precond_U", ctypes.c_void_p), ("precond_lam", ctypes.c_void_p)]
+                ("precond_U", ctypes.c_void_p), ("precond_lam", ctypes.c_void_p),
+                ("progress", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -372,7 +373,7 @@ def _chain_outputs(outputs, names, nc, dev, cg_iters):
 
 
 def _hmc_params(n_steps, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_total, n_points,
-                offsets, X):
+                offsets, X, progress=None):
     """gp_hmc_params; inv_mass: host sequence (one instance's n_theta, or all instances' packed),
     precond: (U, lam) tensors packed per instance (gp_hmc_params in include/gpk.h), or None.
     Returns (params, keep-alive objects)."""
@@ -397,9 +398,12 @@ def _hmc_params(n_steps, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_tota
         _len_at_least(lam, len(n_points) * rank, "precond lam")
         _on_gpu(U, lam)
         pU, plam = _p(U), _p(lam)
+    if progress is not None and (progress.dtype != torch.int32 or progress.numel() < 1 or
+                                 not (progress.is_cuda or progress.is_pinned())):
+        raise ValueError("progress must be a pinned host or device int32 tensor")
     prm = HmcParams(int(n_steps), float(dt), float(cg_tol), int(cg_maxit), int(mode),
                     ctypes.cast(im, ctypes.POINTER(ctypes.c_double)) if im is not None else None,
-                    int(rank), pU, plam)
+                    int(rank), pU, plam, _p(progress))
     return prm, keep
 
 
@@ -410,14 +414,15 @@ def hmc_workspace_size(kernel, params, batch):
 def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, d=None,
                  x_offsets=None, u=None, n_steps=20, dt=1e-2, cg_tol=1e-6, cg_maxit=1000,
                  mode=BATCHED, ws=None, cg_iters=True, prec=None, n_cheb=0, inv_mass=None,
-                 precond=None, outputs=None):
+                 precond=None, outputs=None, progress=None):
     """One HMC trajectory per chain through gp_hmc_leapfrog (packing as in include/gpk.h).
 
     inv_mass: host sequence, the diagonal of M^{-1} packed per instance (None: M = I; a zero
     entry holds that hyperparameter fixed).  precond: (U, lam), a Nystrom factor per instance
     packed as in gp_hmc_params, with which every solve is preconditioned (None: plain CG).
     outputs: the dict an earlier call returned, to be written again (graph mode then replays its
-    captured launch without a new capture).
+    captured launch without a new capture).  progress: a pinned host (or device) int32 tensor into
+    which the batched scheduler writes the number of finished chains while it runs.
 
     theta, pi and x_warm are updated in place.  Returns dict(H0, H1, accepted, status, cg_iters).
     The workspace is kept per (device, size) so repeated calls reuse it (and a captured graph).
@@ -435,7 +440,7 @@ def hmc_leapfrog(X, y, phi, theta, pi, x_warm, kind, n_points, offsets, chains, 
                              dims, x_offsets, n_cheb)
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
     prm, _keep = _hmc_params(n_steps, dt, cg_tol, cg_maxit, mode, inv_mass, precond, nth_total,
-                             n_points, offsets, X)
+                             n_points, offsets, X, progress)
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
     offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
     dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
