@@ -1,20 +1,23 @@
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-cpu] [--no-ard64]
-                    [--no-precond] [--no-implicit]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-leapfrog] [--no-leapfrog-full]
+                    [--no-cpu] [--no-ard8] [--no-ard64] [--no-precond] [--no-implicit] [--no-small]
+                    [--no-cheb2d]
 
 A step is one fused gp_quadform_grad pass over the large3 workload (N = 2^20 points uniform in
 [0,1]^3, isotropic SE kernel l = 0.05, alpha = 1, sigma^2 = 1e-3, 32 N(0,1) auxiliary vectors Z):
 A Z, q_c = z_c^T A z_c and grad_theta sum_c q_c in one pass over all N^2 pairs.  Inputs are
 resident in HBM before the timed region.  The value is pair evaluations per second (N^2 per
 step).  The JSON line also carries the roofline of the dominant kernel (the matrix-core pair
-kernel), the FP64 oracle timed on a bounded row slab of the same workload on the host cores,
-a sampled parity check of the timed outputs, the batched-vs-plain HMC leapfrog comparison on the
-batched workload (64 instances, 8 chains each, 20-step trajectories) with phi drawn by the
-device Gibbs refresh (timed as its own leg), the d = 64 workload in the bfloat16 cross-term
-precision (product and force-pass rates, one short trajectory), plain CG against
-Nystrom-preconditioned CG on the ard8 workload, and one implicit-midpoint trajectory (Anderson
-acceleration, Nystrom-based R) against the plain leapfrog trajectory of the same chain.
+kernel); the FP64 oracle timed on a bounded row slab of the same workload on the host cores,
+which also checks rows of the timed outputs, and the oracle's exact-solve leapfrog on the FP64
+workload; identities of the timed outputs; the HMC leapfrog legs on the batched workload (64
+instances, 8 chains each, 20-step trajectories; phi by the device Gibbs refresh): graph replay,
+Nystrom-preconditioned graph replay and plain mode on a subset, and all 64 instances in one
+preconditioned launch; the ARD d = 8 forward/backward rates; the d = 64 workload in the bfloat16
+cross-term precision; plain against Nystrom-preconditioned CG; the FP64 workload in three modes;
+the Chebyshev-kernel stand-in of the paper's satellite-data run; and one implicit-midpoint
+trajectory.  Every leg states its error against an FP64 reference.
 """
 from __future__ import annotations
 
@@ -125,30 +128,25 @@ def bench_large3(steps, warmup, tune=True, tune_load=None, tune_save=None):
     return {"w": w, "res": res, "wall": wall, "per_call": per, "n": n, "r": r, "tuned": tuned}
 
 
-def parity_sample(b, n_rows=6):
-    """Sampled rows of A Z and the gradient's alpha / sigma^2 identities against the oracle."""
-    from oracle import gp as ogp
-
+def parity_sample(b):
+    """Identities of the timed outputs that hold at any size (no reference computation): the
+    alpha-gradient equals sum_c q_c - sigma^2 |Z|^2 and the sigma^2-gradient equals sigma^2 |Z|^2.
+    Rows of A Z are checked against the oracle inside the CPU baseline leg."""
     w, res = b["w"], b["res"]
-    X = np.asarray(w["X"], np.float32).astype(np.float64)
     Z = np.asarray(w["Z"], np.float32).astype(np.float64)
-    rows = np.random.default_rng(0).choice(b["n"], n_rows, replace=False)
-    AZ = res["AU"][rows].double().cpu().numpy()
-    ref = ogp.matvec(X, w["theta"], "iso", Z, rows=rows)
-    err_rows = float(np.max(np.abs(AZ - ref) / np.linalg.norm(ref, axis=0)[None, :] * np.sqrt(n_rows)))
-    # sum_c q_c - sigma^2 |Z|^2 equals dQ/dlog alpha; dQ/dlog sigma^2 = sigma^2 |Z|^2
     s2 = float(np.exp(w["theta"][2]))
     zz = float(np.sum(Z * Z))
     g = res["grad"].cpu().numpy()
     q = res["quad"].cpu().numpy()
     err_alpha = abs(g[0] - (q.sum() - s2 * zz)) / abs(g[0])
     err_sigma = abs(g[2] - s2 * zz) / abs(g[2])
-    return {"rows_checked": int(n_rows), "rel_err_AZ_rows": err_rows,
-            "rel_err_grad_alpha_identity": float(err_alpha), "rel_err_grad_sigma2": float(err_sigma)}
+    return {"rel_err_grad_alpha_identity": float(err_alpha), "rel_err_grad_sigma2": float(err_sigma)}
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle on a row slab of the large3 workload (all 2^20 columns)."""
+def cpu_baseline(budget_s=15.0, gpu_res=None):
+    """The FP64 oracle on a row slab of the large3 workload (all 2^20 columns); the same slab
+    checks the timed GPU pass (rows of A Z, componentwise); and the oracle's exact-solve
+    leapfrog on the FP64 N = 1024 workload, timed (a different algorithm: Cholesky per step)."""
     from oracle import gp as ogp
     from paper_2412_20884_amd import inputs
 
@@ -165,21 +163,51 @@ def cpu_baseline(budget_s=15.0):
     m = (m // workers) * workers
     rows = np.arange(m)
     t0 = time.perf_counter()
-    ogp.quadform_grad(X, w["theta"], "iso", Z, Z, rows=rows, workers=workers)
+    slab = ogp.quadform_grad(X, w["theta"], "iso", Z, Z, rows=rows, workers=workers)
     t = time.perf_counter() - t0
-    cpu_model = "unknown"
+    parity = None
+    if gpu_res is not None:
+        k = min(m, 64)
+        got = gpu_res["AU"][:k].double().cpu().numpy()
+        ref = slab["AU"][:k]
+        absref = ogp.matvec(X, w["theta"], "iso", np.abs(Z), rows=np.arange(k))
+        parity = {"rows": k, "componentwise_rel_err_AZ": float(np.max(np.abs(got - ref) / absref)),
+                  "col_rel_err_AZ": float(np.max(np.linalg.norm(got - ref, axis=0) /
+                                                 np.linalg.norm(ref, axis=0)))}
+    # the oracle's trajectory on the FP64 workload (phi an exact conditional draw by the
+    # oracle's own Cholesky factor), timed
+    from scipy.linalg import cho_factor, solve_triangular
+
+    from oracle import hmc as ohmc
+    sw = inputs.small_fp64()
+    Lc = cho_factor(ogp.a_matrix(sw["X"], sw["theta"], "iso"), lower=True)[0]
+    phi = solve_triangular(np.tril(Lc).T, sw["xi"], lower=False)
+    t0 = time.perf_counter()
+    ohmc.leapfrog(sw["X"], "iso", sw["y"], phi, sw["theta"], sw["pi"], sw["dt"], sw["n_steps"])
+    t_lf = time.perf_counter() - t0
+    cpu = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    cpu_model = line.split(":", 1)[1].strip()
-                    break
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key in ("model name", "vendor_id", "cpu family", "model", "stepping", "cpu MHz") \
+                        and key not in cpu:
+                    cpu[key] = val.strip()
     except OSError:
         pass
-    return {"value": m * n / t, "unit": "pair-evals/s", "cores": workers, "cpu_model": cpu_model,
+    return {"value": m * n / t, "unit": "pair-evals/s", "cores": workers,
+            "threads": {"workers": workers, "blas_omp": os.environ.get("OMP_NUM_THREADS"),
+                        "host_cpus_visible": os.cpu_count()},
+            "cpu_model": cpu.get("model name", "unknown"),
+            "cpu_id": {k: cpu.get(k) for k in ("vendor_id", "cpu family", "model", "stepping", "cpu MHz")},
             "kind": "oracle",
             "sample": f"rows 0..{m - 1} of the large3 workload against all {n} columns "
-                      f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad"}
+                      f"(FP64 numpy, {t:.1f} s wall), fused A Z + q + grad",
+            "parity_of_timed_gpu_pass": parity,
+            "leapfrog_small_fp64": {"chain_steps_per_s": sw["n_steps"] / t_lf, "seconds": t_lf,
+                                    "algorithm": "exact Cholesky solves per step (not CG), FP64 numpy",
+                                    "workload": "N=1024, d=2, one chain, 100 leapfrog steps of 1e-2"}}
 
 
 def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0, rwm=True,
@@ -440,6 +468,20 @@ def bench_ard64(n_chain_steps=4, chains=1, dt=None):
         t = float(np.median(ts))
         out[name] = {"seconds": t, "pair_evals_per_s": n * n / t}
         log(f"ard64 {name}: {out[name]}")
+    # error against the library's FP64 path (direct differences): the whole product and its
+    # off-diagonal part (K - alpha I) V against that part's own norm
+    got = gpk.kmatvec(X, th, V, "ard", prec="bf16x", ws=ws).double()
+    Vd = V.double()
+    ref = gpk.kmatvec(X.double(), th, Vd, "ard")
+    torch.cuda.synchronize()
+    diag = float(np.exp(wl["theta"][0]) + np.exp(wl["theta"][-1]))
+    od_g, od_r = got - diag * Vd, ref - diag * Vd
+    out["error_vs_fp64"] = {
+        "product": float(((got - ref).norm(dim=0) / ref.norm(dim=0)).max()),
+        "offdiagonal_part": float(((od_g - od_r).norm(dim=0) / od_r.norm(dim=0)).max()),
+        "offdiagonal_norm_over_column": float((od_r.norm(dim=0) / ref.norm(dim=0)).min()),
+        "budget": 3e-3, "reference": "the library's FP64 kernels on the same inputs, all rows"}
+    log(f"ard64 error vs FP64: {out['error_vs_fp64']}")
     # trajectories chain by chain (plain mode: GP_BF16X runs through the product kernels), each
     # after its own phi refresh, with a progress line per chain
     t_traj, t_phi, its, acc, sts, dhs, phi_its = 0.0, 0.0, 0, 0, [], [], []
@@ -556,6 +598,83 @@ def bench_small_fp64(tol=1e-6):
                      "dH": float(r["H1"][0] - r["H0"][0]), "accepted": int(r["accepted"][0]),
                      "status": int(r["status"][0])}
         log(f"small_fp64 {name}: {out[name]}")
+        if name == "graph":
+            th_gpu, pi_gpu = th.cpu().numpy(), pi.cpu().numpy()
+    # error of the production-tolerance trajectory against the same trajectory with the solves
+    # at 1e-13 (the FP64 path; the oracle's exact-solve trajectory is matched to 1e-8 in the tests)
+    th = th0.clone()
+    pi = torch.tensor(wl["pi"], dtype=torch.float64, device=dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    gpk.hmc_leapfrog(X.view(-1, 1), y, phi, th, pi, x, "iso", [n], [0], 1, d=[2], n_steps=wl["n_steps"],
+                     dt=wl["dt"], cg_tol=1e-13, cg_maxit=5000, mode=gpk.GRAPH)
+    torch.cuda.synchronize()
+    out["graph_vs_tight_fp64"] = {"max_abs_theta_err": float(np.max(np.abs(th_gpu - th.cpu().numpy()))),
+                                  "max_abs_pi_err": float(np.max(np.abs(pi_gpu - pi.cpu().numpy()))),
+                                  "note": f"CG tolerance {tol:g} against 1e-13, same inputs"}
+    log(f"small_fp64 error: {out['graph_vs_tight_fp64']}")
+    return out
+
+
+def bench_ard8(reps=5):
+    """The ARD workload (N = 65,536, d = 8, FP32, R = 16): the autograd forward A(theta) V and
+    its hand-written backward (one gp_quadform_grad pass with U = G, V = V: theta-gradient and
+    A G), pair-evals/s and flop rate by the counting convention (forward 3d + 2 + 2R = 58 flop
+    per pair, backward 4R + 6d + 4 = 116), and the error against the library's FP64 path
+    (componentwise for the products, condition-scaled for the gradient)."""
+    import torch
+
+    from paper_2412_20884_amd import gpk, inputs
+
+    dev = "cuda:0"
+    wl = inputs.ard8()
+    n, d = wl["X"].shape
+    r = wl["V"].shape[1]
+    X32 = np.asarray(wl["X"], np.float32)
+    V32 = np.asarray(wl["V"], np.float32)
+    G32 = np.asarray(wl["G"], np.float32)
+    X = torch.tensor(X32, device=dev)
+    V = torch.tensor(V32, device=dev)
+    G = torch.tensor(G32, device=dev)
+    th = torch.tensor(wl["theta"], dtype=torch.float64, device=dev)
+    ws = torch.empty(gpk.workspace_size(gpk.make_kernel("ard", X), n, r), dtype=torch.uint8, device=dev)
+    out = {"workload": f"ard8: N={n} points N(0, I_8), ARD SE (l_k log-uniform [0.3, 3]), sigma^2=1e-2, "
+                       f"FP32, R={r}: forward A V and backward (grad_theta, A G) of KMatVec", "N": n, "d": d}
+    res = {}
+    for name, fn, flop in (
+            ("forward", lambda: gpk.kmatvec(X, th, V, "ard", ws=ws), 3 * d + 2 + 2 * r),
+            ("backward", lambda: gpk.quadform_grad(X, th, G, V, None, "ard", want_quad=False,
+                                                   want_AU=True, ws=ws), 4 * r + 6 * d + 4)):
+        res[name] = fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = float(np.median(ts))
+        out[name] = {"seconds": t, "pair_evals_per_s": n * n / t, "flop_per_pair": flop,
+                     "tflop_per_s": flop * n * n / t / 1e12,
+                     "frac_of_fp16_mfma_peak": flop * n * n / t / PEAK_F16_MFMA,
+                     "kernel": "pair_mfma (R = 16: fp16 hi/lo matrix-core contractions)"}
+    # error against the library's FP64 path on the same (rounded) inputs
+    Xd, Vd, Gd = X.double(), V.double(), G.double()
+    ref_f = gpk.kmatvec(Xd, th, Vd, "ard")
+    abs_f = gpk.kmatvec(Xd, th, Vd.abs(), "ard")
+    ref_b = gpk.quadform_grad(Xd, th, Gd, Vd, None, "ard", want_quad=False, want_AU=True)
+    abs_b = gpk.quadform_grad(Xd, th, Gd.abs(), Vd.abs(), None, "ard", want_quad=False, want_AU=True)
+    torch.cuda.synchronize()
+    out["error_vs_fp64_path"] = {
+        "forward_componentwise": float(((res["forward"].double() - ref_f).abs() / abs_f).max()),
+        "backward_AG_componentwise": float(((res["backward"]["AU"].double() - ref_b["AU"]).abs()
+                                            / abs_b["AU"]).max()),
+        "grad_theta_condition_scaled": float(((res["backward"]["grad"] - ref_b["grad"]).abs()
+                                              / abs_b["grad"]).max()),
+        "reference": "the library's FP64 kernels on the same inputs (checked against the oracle "
+                     "at 1e-11 in the tests)"}
+    log(f"ard8: {out}")
     return out
 
 
@@ -729,6 +848,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ard64", action="store_true")
+    ap.add_argument("--no-ard8", action="store_true", help="leave out the ARD d = 8 forward/backward leg")
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-implicit", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="leave out the FP64 N = 1024 leg")
@@ -763,7 +883,8 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["wall"] / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (the two R-contractions as fp16 hi/lo splits, 3 MFMA products each, f32 accumulate)",
         "data": "synthetic",
         "config": {"workload": "large3: N=2^20 points uniform in [0,1]^3, isotropic SE l=0.05, alpha=1, "
                                "sigma^2=1e-3, 32 N(0,1) auxiliary vectors; fused A Z + z_c^T A z_c + grad_theta",
@@ -773,7 +894,6 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "pair_mfma<3,32,1> (fp16 hi/lo split, 3 products per contraction)",
                      "flop_per_pair": FLOP_PER_PAIR,
-                     "frac_of_fp32_vector_peak": achieved / PEAK_F32_VECTOR,
                      "issue_bound_cycles_per_pair_slot": SLOT_CYCLES,
                      "issue_bound_pair_evals_per_s": ISSUE_BOUND_PAIRS,
                      "frac_of_issue_bound": pairs_per_s_kernel / ISSUE_BOUND_PAIRS},
@@ -782,7 +902,7 @@ def main():
     }
     if not args.no_cpu:
         log("cpu baseline: timing the FP64 oracle on a row slab")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_budget, b["res"])
     if not args.no_leapfrog:
         line["leapfrog"] = bench_leapfrog(tuple(args.leapfrog_modes.split(",")), args.leapfrog_subset,
                                           args.leapfrog_group, not args.no_rwm,
@@ -792,6 +912,8 @@ def main():
         # Nystrom-preconditioned, graph-replayed
         line["leapfrog_full"] = bench_leapfrog(("graph_nystrom",), 1, 0, False,
                                                args.leapfrog_precond_rank)
+    if not args.no_ard8:
+        line["ard8_fwd_bwd"] = bench_ard8()
     if not args.no_ard64:
         line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt)
     if not args.no_precond:
