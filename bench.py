@@ -436,16 +436,20 @@ def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0,
     return out
 
 
-def bench_ard64(n_chain_steps=4, chains=1, dt=None):
+def bench_ard64(n_chain_steps=5, chains=16, dt=None, plain_chains=2):
     """The d = 64 workload with GP_BF16X (bfloat16 cross term, compensated norms): rates of the
     product (R = 1, one CG iteration) and of the fused force pass (R = 2, [x | phi] with
-    w = (-1/2, 1/2)), and one short plain-mode trajectory of one chain."""
+    w = (-1/2, 1/2)) through the product entry points, their error against FP64, and the
+    trajectories: every chain's phi from one device Gibbs refresh (the chains share theta_0, so one
+    multi-shift call with one column per chain), then all chains in one graph-replayed persistent
+    launch, against the plain mode (per-op launches) on the first `plain_chains` chains of the
+    same inputs."""
     import torch
 
     from paper_2412_20884_amd import gpk, inputs
 
     dev = "cuda:0"
-    wl = inputs.ard64()
+    wl = inputs.ard64(chains=max(chains, 1))
     n = wl["X"].shape[0]
     X = torch.tensor(wl["X"], dtype=torch.float32, device=dev)
     th = torch.tensor(wl["theta"], dtype=torch.float64, device=dev)
@@ -482,43 +486,54 @@ def bench_ard64(n_chain_steps=4, chains=1, dt=None):
         "offdiagonal_norm_over_column": float((od_r.norm(dim=0) / ref.norm(dim=0)).min()),
         "budget": 3e-3, "reference": "the library's FP64 kernels on the same inputs, all rows"}
     log(f"ard64 error vs FP64: {out['error_vs_fp64']}")
-    # trajectories chain by chain (plain mode: GP_BF16X runs through the product kernels), each
-    # after its own phi refresh, with a progress line per chain
-    t_traj, t_phi, its, acc, sts, dhs, phi_its = 0.0, 0.0, 0, 0, [], [], []
-    for h in range(chains):
-        t0 = time.perf_counter()
-        phi = gpk.phi_refresh(X, th, torch.tensor(wl["xi"][h], dtype=torch.float32, device=dev), "ard",
-                              prec="bf16x", tol=1e-6, maxit=500)
+    del got, ref, Vd, od_g, od_r, ws
+    if chains < 1:
+        return out
+    dt = dt or wl["dt"]
+    # phi for every chain at theta_0: one refresh, one column per chain
+    xi = torch.tensor(wl["xi"][:chains].T.copy(), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph = gpk.phi_refresh(X, th, xi, "ard", prec="bf16x", tol=1e-6, maxit=500)
+    torch.cuda.synchronize()
+    t_phi = time.perf_counter() - t0
+    phi = ph["phi"].T.contiguous().view(-1)  # [chain][n]
+    out["phi_refresh"] = {"seconds": t_phi, "chains": chains, "iterations": int(ph["iters"].max())}
+    log(f"ard64 phi refresh: {out['phi_refresh']}")
+    th0 = np.tile(wl["theta"], chains)
+    pi0 = wl["pi"][:chains].ravel()
+    u = torch.tensor(wl["u"][:chains], dtype=torch.float64, device=dev)
+    res = {}
+    for mode, nch in (("graph", chains), ("plain", min(plain_chains, chains))):
+        thc = torch.tensor(th0[:66 * nch], dtype=torch.float64, device=dev)
+        pi = torch.tensor(pi0[:66 * nch], dtype=torch.float64, device=dev)
+        x = torch.zeros(nch * n, dtype=torch.float32, device=dev)
+        md = gpk.GRAPH if mode == "graph" else gpk.PLAIN
         torch.cuda.synchronize()
-        t_phi += time.perf_counter() - t0
-        phi_its.append(int(phi["iters"][0]))
-        thc = th.clone()
-        pi = torch.tensor(wl["pi"][h], dtype=torch.float64, device=dev)
-        x = torch.zeros(n, dtype=torch.float32, device=dev)
-        u = torch.tensor([wl["u"][h]], dtype=torch.float64, device=dev) if chains > 1 else None
         t0 = time.perf_counter()
-        r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi["phi"].contiguous(), thc, pi, x, "ard", [n], [0], 1,
-                             d=[64], u=u, n_steps=n_chain_steps, dt=dt or wl["dt"], cg_tol=1e-6, cg_maxit=500,
-                             mode=gpk.PLAIN, prec="bf16x")
+        r = gpk.hmc_leapfrog(X.view(-1, 1), y, phi[:nch * n], thc, pi, x, "ard", [n], [0], nch,
+                             d=[64], u=u[:nch], n_steps=n_chain_steps, dt=dt, cg_tol=1e-6,
+                             cg_maxit=500, mode=md, prec="bf16x")
         torch.cuda.synchronize()
-        t_traj += time.perf_counter() - t0
-        its += int(r["cg_iters"][0])
-        acc += int(r["accepted"][0])
-        sts.append(int(r["status"][0]))
-        dhs.append(float(r["H1"][0]) - float(r["H0"][0]))
-        if chains > 1:
-            log(f"  ard64 chain {h}: cumulative {t_traj:.1f} s, dH {dhs[-1]:.3g}")
-    out["phi_refresh_iterations"] = phi_its[0] if chains == 1 else phi_its
-    out["trajectory"] = {"chains": chains, "chain_steps": chains * n_chain_steps, "seconds": t_traj,
-                         "chain_steps_per_s": chains * n_chain_steps / t_traj,
-                         "cg_iterations": its, "status": sts[0] if chains == 1 else sts,
-                         "dH": dhs[0] if chains == 1 else [min(dhs), max(dhs)]}
-    if chains > 1:
-        out["trajectory"]["accept_rate"] = acc / chains
-        out["trajectory"]["phi_refresh_seconds"] = t_phi
-        out["trajectory"]["workload"] = (f"{chains} chains x {n_chain_steps} leapfrog steps of dt "
-                                         f"{dt or wl['dt']:g}, one chain per call, each after its phi refresh")
-    log(f"ard64 trajectory: {out['trajectory']}")
+        t = time.perf_counter() - t0
+        dh = (r["H1"] - r["H0"]).cpu().numpy()
+        res[mode] = {"theta": thc.cpu().numpy(), "H1": r["H1"].cpu().numpy()}
+        out[f"trajectories_{mode}"] = {
+            "chains": nch, "chain_steps": nch * n_chain_steps, "seconds": t,
+            "chain_steps_per_s": nch * n_chain_steps / t,
+            "cg_iterations_per_chain": float(r["cg_iters"].double().mean()),
+            "accept_rate": float(r["accepted"].double().mean()),
+            "status_nonzero": int((r["status"] != 0).sum()),
+            "dH_range": [float(dh.min()), float(dh.max())]}
+        log(f"ard64 trajectories {mode}: {out[f'trajectories_{mode}']}")
+    k = 66 * min(plain_chains, chains)
+    out["graph_vs_plain"] = {
+        "max_abs_theta_diff": float(np.max(np.abs(res["graph"]["theta"][:k] - res["plain"]["theta"]))),
+        "note": "the same matrix-core tiles in both modes, one job per launch in plain mode"}
+    out["speedup_batched_vs_plain"] = (out["trajectories_graph"]["chain_steps_per_s"]
+                                       / out["trajectories_plain"]["chain_steps_per_s"])
+    out["trajectory_workload"] = (f"{chains} chains x {n_chain_steps} leapfrog steps of dt {dt:g}, "
+                                  f"CG tol 1e-6, phi from the device Gibbs refresh")
     return out
 
 
@@ -842,8 +857,10 @@ def main():
     ap.add_argument("--leapfrog-group", type=int, default=0,
                     help="instances per persistent launch in the batched modes (0: all in one)")
     ap.add_argument("--no-rwm", action="store_true", help="leave out the random-walk Metropolis leg")
-    ap.add_argument("--ard64-chains", type=int, default=1, help="chains of the d = 64 trajectory leg")
-    ap.add_argument("--ard64-steps", type=int, default=4, help="leapfrog steps per d = 64 trajectory")
+    ap.add_argument("--ard64-chains", type=int, default=16, help="chains of the d = 64 trajectory leg")
+    ap.add_argument("--ard64-steps", type=int, default=5, help="leapfrog steps per d = 64 trajectory")
+    ap.add_argument("--ard64-plain-chains", type=int, default=2,
+                    help="chains of the d = 64 leg's plain-mode comparison")
     ap.add_argument("--ard64-dt", type=float, default=None, help="leapfrog step of the d = 64 leg")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
@@ -915,7 +932,8 @@ def main():
     if not args.no_ard8:
         line["ard8_fwd_bwd"] = bench_ard8()
     if not args.no_ard64:
-        line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt)
+        line["ard64_bf16x"] = bench_ard64(args.ard64_steps, args.ard64_chains, args.ard64_dt,
+                                          args.ard64_plain_chains)
     if not args.no_precond:
         line["nystrom_precond"] = bench_precond()
     if not args.no_implicit:

@@ -8,7 +8,7 @@
 namespace gpk {
 
 // Jobs a chain can publish; every job is split into n_rb row blocks x n_cs column splits.
-enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3, kJobZ = 4 };
+enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3, kJobZ = 4, kJobStage = 5 };
 // Why the current solve + quadratic-form pass is being done.
 enum HmcCtxKind { kCtxEnergy0 = 0, kCtxForce = 1, kCtxEnergy1 = 2 };
 
@@ -18,6 +18,32 @@ constexpr int kHmcRec = 80;
 constexpr int kHmcTile = 256;      // rows per tile (one per thread)
 constexpr int kHmcMaxTheta = kMaxD + 2;
 constexpr int kHmcMaxRank = 512;   // largest Nystrom rank of the preconditioned solves
+
+// Geometry of the GP_BF16X trajectory jobs: 32-column tiles whose LDS image is the bfloat16 hi
+// and lo coordinate rows (padded to XSTR halves against bank conflicts), the 32 norms, the column
+// operand (up to 2 floats per column) and, for the force pass of ARD chains, the image of
+// [X~ | 1]^T: KB2 blocks of 16 rows of kStr halves (slot-ordered columns) of hi parts, then the
+// KB2 - 1 blocks of lo parts of X~ (the ones row needs none).
+namespace xmt {
+constexpr int TJ = 32;           // columns per tile
+constexpr int kStr = 40;         // halves per row of the transposed column image
+constexpr int kRowsStage = 64;   // rows per stage job (one job id)
+constexpr int kRowsJob = 128;    // rows per product or force-pass job
+template <int DPX>
+struct Geo {
+  static constexpr int XSTR = DPX + 8;
+  static constexpr int KB2 = DPX / 16 + 1;
+  static constexpr int kXB = TJ * XSTR * 2;
+  static constexpr int kNB = TJ * 4;
+  static constexpr int kVB = TJ * 2 * 4;
+  static constexpr int kBBH = KB2 * 16 * kStr * 2;
+  static constexpr int kBBL = (KB2 - 1) * 16 * kStr * 2;
+  static constexpr int kBB = kBBH + kBBL;  // bytes of one tile's [X~ | 1]^T image
+  static constexpr int oXL = kXB, oN = 2 * kXB, oV = oN + kNB, oBH = oV + kVB, oBL = oBH + kBBH;
+  static constexpr int kBytes = oBH + kBB;
+};
+inline int dpx_of(int d) { return d <= 32 ? 32 : 64; }
+}  // namespace xmt
 
 template <typename T>
 struct HmcChain {
@@ -66,11 +92,16 @@ struct HmcChain {
   int jobs_run;  // jobs completed in this trajectory (bounded, see HmcRunParams::max_jobs)
   double rr, yy, H0, H1;
   double rz;  // r^T z of the preconditioned CG (z = P^{-1} r)
-  // External products (GP_BF16X, plain mode): the jobs run as gp_kmatvec / gp_quadform_grad
-  // passes that write q in full, or the force and the two forms into ext_res.
-  int ext;
-  double ext_w[2];                     // (-1/2, +1/2)
-  double ext_res[kHmcMaxTheta + 2];    // gradient, then x^T A x and phi^T A phi
+  // GP_BF16X chains (xm = padded cross-term width 32 or 64, else 0): the squared distances come
+  // from the norm expansion with the cross term on the matrix cores.  A stage job (64 rows per
+  // job) writes, for every theta, the bfloat16 hi / lo coordinates xh, xl ([n_rb * 64][xm + 8],
+  // rows past n zero), the compensated norms nrm (rows past n: 1e30, so their kernel values
+  // vanish) and, for ARD chains, bimg: the column-side image of [X~ | 1]^T per 32-column tile
+  // (Geo::kBB bytes a tile, bfloat16 in slot order).
+  int xm;
+  uint16_t *xh, *xl, *bimg;
+  float *nrm;
+  double cscale[kMaxD];  // per-dimension coordinate scale of the theta being solved at
 };
 
 struct HmcRunParams {

@@ -20,16 +20,16 @@ gp_status hip_fail(hipError_t e, const char *where);
 
 hipError_t hmc_kickoff_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
 hipError_t hmc_kickoff_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, hipStream_t);
-hipError_t hmc_tiles_f32(void *, int, int, int, int, hipStream_t);
-hipError_t hmc_tiles_f64(void *, int, int, int, int, hipStream_t);
+hipError_t hmc_tiles_f32(void *, int, int, int, int, int, hipStream_t);
+hipError_t hmc_tiles_f64(void *, int, int, int, int, int, hipStream_t);
 hipError_t hmc_epilogue_f32(void *, const HmcRunParams &, int, hipStream_t);
 hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, int, hipStream_t);
 hipError_t hmc_gather_f32(void *, int, int, hipStream_t);
 hipError_t hmc_gather_f64(void *, int, int, hipStream_t);
 hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, int, hipStream_t);
+                              int, int, int, int, hipStream_t);
 hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, int, hipStream_t);
+                              int, int, int, int, hipStream_t);
 hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
 hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
 hipError_t hmc_check_f32(void *, int, hipStream_t);
@@ -46,7 +46,7 @@ struct InstInfo {
 constexpr int kMaxPrecondRank = kHmcMaxRank;
 
 struct ChainLayout {
-  size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains, prod, prod_bytes;
+  size_t hdr_word, hdr_fin, hdr_cnt, hdr_order, chains;
   std::vector<size_t> per_chain;  // offset of each chain's region
   std::vector<int> n_rb, n_cs;
   size_t total;
@@ -54,11 +54,24 @@ struct ChainLayout {
 
 size_t chain_bytes(int prec) { return prec == GP_F64 ? sizeof(HmcChain<double>) : sizeof(HmcChain<float>); }
 
-// Chains whose jobs run through the product entry points (gp_kmatvec / gp_quadform_grad) rather
-// than the tile kernels: the bfloat16 cross term.
-bool uses_ext(int prec, int kind) {
-  (void)kind;
-  return prec == GP_BF16X;
+// Padded cross-term width of a GP_BF16X chain (its jobs run on the matrix-core tiles), else 0.
+int xm_width(int prec, int d) { return prec == GP_BF16X ? xmt::dpx_of(d) : 0; }
+
+// Row blocks of a chain's jobs: 256-row tiles, or the 64-row stage / force-pass blocks of a
+// GP_BF16X chain (its 128-row product jobs use the first half of the ids).
+int64_t row_blocks(int64_t n, int xm) {
+  const int64_t rows = xm ? xmt::kRowsStage : kHmcTile;
+  return (n + rows - 1) / rows;
+}
+
+template <int DPX>
+size_t xm_bytes(int64_t n_rb, int ard) {
+  using G = xmt::Geo<DPX>;
+  const int64_t nrow = n_rb * xmt::kRowsStage;
+  size_t o = 2 * align256(2 * (size_t)nrow * G::XSTR);            // xh, xl
+  o += align256(4 * (size_t)nrow);                               // nrm
+  if (ard) o += align256((size_t)(nrow / xmt::TJ) * G::kBB);  // bimg
+  return o;
 }
 
 constexpr int kPlainCheck = 4;  // plain mode: jobs between host checks of a tile chain
@@ -71,11 +84,13 @@ int plain_splits(int64_t n) {
   return (int)std::max<int64_t>(1, s);
 }
 
-size_t region_bytes(const InstInfo &in, int prec, int n_cs, int prank) {
+size_t region_bytes(const InstInfo &in, int prec, int kind, int n_cs, int prank) {
   const size_t es = prec == GP_F64 ? 8 : 4;
   const int64_t n = in.n;
-  const int n_rb = (int)((n + kHmcTile - 1) / kHmcTile);
+  const int xm = xm_width(prec, in.d);
+  const int n_rb = (int)row_blocks(n, xm);
   size_t o = 0;
+  if (xm) o += xm == 64 ? xm_bytes<64>(n_rb, kind == GP_SE_ARD) : xm_bytes<32>(n_rb, kind == GP_SE_ARD);
   o += align256(es * n * in.dp);     // xs
   o += 4 * align256(es * n);         // r, p, q, x0
   o += align256(es * 2 * n);         // Z
@@ -102,31 +117,17 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
   L.chains = o;
   o = align256(o + chain_bytes(prec) * (size_t)nc);
   for (const InstInfo &in : inst) {
-    const int n_cs = (mode == GP_HMC_PLAIN && !uses_ext(prec, kind)) ? plain_splits(in.n) : 1;
-    const int n_rb = (int)((in.n + kHmcTile - 1) / kHmcTile);
+    const int xm = xm_width(prec, in.d);
+    const int n_cs = (mode == GP_HMC_PLAIN && !xm) ? plain_splits(in.n) : 1;
+    const int n_rb = (int)row_blocks(in.n, xm);
     for (int h = 0; h < chains; ++h) {
       L.per_chain.push_back(o);
       L.n_rb.push_back(n_rb);
       L.n_cs.push_back(n_cs);
-      o += region_bytes(in, prec, n_cs, prank);
+      o += region_bytes(in, prec, kind, n_cs, prank);
     }
   }
-  L.prod = o;
-  L.prod_bytes = 0;
-  if (uses_ext(prec, kind)) {
-    // one product workspace, reused by every (sequentially processed) chain
-    for (const InstInfo &in : inst) {
-      gp_kernel kk;
-      kk.kind = kind;
-      kk.prec = prec;
-      kk.d = in.d;
-      kk.flags = 0;
-      kk.n_cheb = n_cheb;
-      const size_t b = gp_workspace_size(&kk, in.n, 2);
-      if (b > L.prod_bytes) L.prod_bytes = b;
-    }
-    o += align256(L.prod_bytes);
-  }
+  (void)n_cheb;
   L.total = o;
   return L;
 }
@@ -145,9 +146,11 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   if (p->cg_maxit < 1) return fail(GP_ERR_ARG, "cg_maxit must be >= 1");
   if (p->mode != GP_HMC_PLAIN && p->mode != GP_HMC_BATCHED && p->mode != GP_HMC_GRAPH)
     return fail(GP_ERR_ARG, "unknown mode %d", p->mode);
-  if (uses_ext(k->prec, k->kind) && p->mode != GP_HMC_PLAIN)
-    return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories run in GP_HMC_PLAIN mode");
-  if (uses_ext(k->prec, k->kind) && p->precond_rank > 0)
+  if (k->prec == GP_BF16X && k->kind == GP_SE_CHEB)
+    return fail(GP_ERR_UNSUPPORTED,
+                "GP_BF16X trajectories take GP_SE_ISO or GP_SE_ARD (the Chebyshev-amplitude kernel "
+                "has d <= 6, where the cross term gains nothing)");
+  if (k->prec == GP_BF16X && p->precond_rank > 0)
     return fail(GP_ERR_UNSUPPORTED, "GP_BF16X trajectories take no preconditioner");
   if (!b) return fail(GP_ERR_ARG, "batch is NULL");
   if (b->n_inst < 1 || b->chains_per_inst < 1)
@@ -213,7 +216,7 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
                  char *ws, const gp_hmc_params *p,
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
-                 int32_t *status, int32_t *iters, int ext, std::vector<HmcChain<T>> &out) {
+                 int32_t *status, int32_t *iters, int prec, std::vector<HmcChain<T>> &out) {
   out.assign(inst.size() * chains, HmcChain<T>());
   int64_t tofs = 0;
   int c = 0;
@@ -250,6 +253,22 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
       char *r = ws + L.per_chain[c];
       const size_t es = sizeof(T);
       const int64_t n = in.n;
+      ch.xm = xm_width(prec, in.d);
+      if (ch.xm) {
+        const int64_t nrow = (int64_t)L.n_rb[c] * xmt::kRowsStage;
+        const int xstr = ch.xm + 8;
+        const int kbb = ch.xm == 64 ? xmt::Geo<64>::kBB : xmt::Geo<32>::kBB;
+        ch.xh = (uint16_t *)r;
+        r += align256(2 * (size_t)nrow * xstr);
+        ch.xl = (uint16_t *)r;
+        r += align256(2 * (size_t)nrow * xstr);
+        ch.nrm = (float *)r;
+        r += align256(4 * (size_t)nrow);
+        if (kind == GP_SE_ARD) {
+          ch.bimg = (uint16_t *)r;
+          r += align256((size_t)(nrow / xmt::TJ) * kbb);
+        }
+      }
       ch.xs = (T *)r;
       r += align256(es * n * in.dp);
       const size_t vb = align256(es * n);
@@ -278,7 +297,6 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
         ch.pg = ch.pgp + (size_t)2 * ch.n_rb * ch.prank;
         ch.ph = ch.pg + ch.prank;
       }
-      ch.ext = ext;
     }
     tofs += in.nth;
   }
@@ -292,23 +310,6 @@ struct GraphEntry {
 std::mutex g_mu;
 std::map<void *, std::vector<char>> g_uploaded;  // ws -> descriptor bytes last uploaded
 std::map<void *, GraphEntry> g_graphs;           // ws -> captured trajectory
-
-// One job of an ext chain: MvX / MvP as q = A x or A p, Qf as the force and the two forms of
-// [x | phi] with w = (-1/2, +1/2) into the chain's ext_res.  `hdesc` holds the chain descriptors
-// as uploaded (device pointers); `cp` is the chain's device copy.
-template <typename T>
-gp_status ext_job(const gp_kernel &kk, const InstInfo &in, int job, const char *hdesc, int c,
-                  void *cp, char *pw, size_t pw_bytes, hipStream_t stream) {
-  const HmcChain<T> *hc = (const HmcChain<T> *)hdesc + c;
-  if (job == kJobMvX || job == kJobMvP) {
-    const T *v = job == kJobMvX ? hc->x : hc->p;
-    return gp_kmatvec(&kk, in.n, hc->X, hc->theta, 1, v, 1, nullptr, hc->q, 1, pw, pw_bytes, stream);
-  }
-  HmcChain<T> *dc = (HmcChain<T> *)cp;
-  return gp_quadform_grad(&kk, in.n, hc->X, hc->theta, 2, hc->Z, 2, hc->Z, 2, dc->ext_w,
-                          dc->ext_res, dc->ext_res + in.nth, nullptr, 0, nullptr, 0, pw, pw_bytes,
-                          stream);
-}
 
 }  // namespace
 }  // namespace gpk
@@ -348,12 +349,12 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
     fill_chains<double>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                        accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
+                        accepted, status, cg_iters, k->prec, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
     fill_chains<float>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                       accepted, status, cg_iters, uses_ext(k->prec, k->kind) ? 1 : 0, v);
+                       accepted, status, cg_iters, k->prec, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
   // chain order for the batched scheduler: largest problems first
@@ -392,9 +393,10 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   prm.dt = p->dt;
   prm.tol2 = p->cg_tol * p->cg_tol;
   prm.cg_maxit = p->cg_maxit;
-  // a preconditioned CG iteration is two jobs (the product and the z job)
+  // a preconditioned CG iteration is two jobs (the product and the z job); a solve adds its
+  // first product, the force pass and (GP_BF16X) the stage job
   const int64_t per_it = p->precond_rank > 0 ? 2 : 1;
-  prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 3) + 4,
+  prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 4) + 4,
                                         (int64_t)1 << 30);
   prm.rwm = rwm;
   HmcQueue qu;
@@ -421,41 +423,28 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
       if (e != hipSuccess) return hip_fail(e, "kickoff");
       const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
       const int n_jobs = L.n_rb[c] * L.n_cs[c];
-      const bool ext = uses_ext(k->prec, k->kind);
-      // tile chains are checked every kPlainCheck jobs: on a finished chain the tiles and the
-      // epilogue do nothing, so a few surplus launches are harmless; ext chains read their job
+      const int xm = xm_width(k->prec, inst[c / chains].d);
+      // chains are checked every kPlainCheck jobs: on a finished chain the tiles and the epilogue
+      // do nothing, so a few surplus launches are harmless
       for (int64_t guard = 0;; ++guard) {
         if (guard > (int64_t)prm.max_jobs + 2 + kPlainCheck)
           return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
         // job .. done are adjacent ints of the chain state: one read brings both
         int state[kJobToDone + 1] = {};
-        if (ext || guard % kPlainCheck == 0) {
+        if (guard % kPlainCheck == 0) {
           e = hipMemcpyAsync(state, (char *)cp + off_job, sizeof(state), hipMemcpyDeviceToHost, stream);
           if (e == hipSuccess) e = hipStreamSynchronize(stream);
           if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
           if (state[kJobToDone]) break;
         }
         const int dpc = inst[c / chains].dp;
-        if (ext) {
-          // the job runs as one call of the product entry points
-          const int job = state[0];
-          const InstInfo &in = inst[c / chains];
-          gp_kernel kk = *k;
-          kk.d = in.d;
-          const gp_status ps = f64 ? ext_job<double>(kk, in, job, desc.data(), c, cp, w + L.prod,
-                                                     L.prod_bytes, stream)
-                                   : ext_job<float>(kk, in, job, desc.data(), c, cp, w + L.prod,
-                                                    L.prod_bytes, stream);
-          if (ps != GP_OK) return ps;
-        } else {
-          e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, ch, pc, stream)
-                  : hmc_tiles_f32(cp, n_jobs, dpc, ch, pc, stream);
-          // with column splits the product is gathered by a multi-workgroup pass before the
-          // (single-workgroup) epilogue
-          if (e == hipSuccess && L.n_cs[c] > 1)
-            e = f64 ? hmc_gather_f64(cp, L.n_rb[c], pc, stream)
-                    : hmc_gather_f32(cp, L.n_rb[c], pc, stream);
-        }
+        e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, ch, pc, 0, stream)
+                : hmc_tiles_f32(cp, n_jobs, dpc, ch, pc, xm, stream);
+        // with column splits the product is gathered by a multi-workgroup pass before the
+        // (single-workgroup) epilogue
+        if (e == hipSuccess && L.n_cs[c] > 1)
+          e = f64 ? hmc_gather_f64(cp, L.n_rb[c], pc, stream)
+                  : hmc_gather_f32(cp, L.n_rb[c], pc, stream);
         if (e == hipSuccess)
           e = f64 ? hmc_epilogue_f64(cp, prm, pc, stream) : hmc_epilogue_f32(cp, prm, pc, stream);
         if (e != hipSuccess) return hip_fail(e, "plain-mode step");
@@ -469,11 +458,16 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev);
+  int dpmax = 4, xmax = 0;
+  for (const InstInfo &in : inst) {
+    dpmax = std::max(dpmax, in.dp);
+    xmax = std::max(xmax, xm_width(k->prec, in.d));
+  }
   int64_t total_jobs = 0;
   for (int c = 0; c < nc; ++c) total_jobs += (int64_t)L.n_rb[c] * L.n_cs[c];
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 4, total_jobs));
-  int dpmax = 4;
-  for (const InstInfo &in : inst) dpmax = std::max(dpmax, in.dp);
+  // as many workgroups as can be resident: 4 per CU, 2 for the GP_BF16X tiles (two 32 KB tile
+  // buffers each)
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * (xmax ? 2 : 4), total_jobs));
   // an idle workgroup gives up after 20 s without claimable work
   const long long idle_limit = (long long)clk_khz * 1000LL * 20LL;
 
@@ -483,8 +477,8 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
             : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, s)
-            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, s);
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, 0, s)
+            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, xmax, s);
     if (r != hipSuccess) return r;
     return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
   };
@@ -501,6 +495,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   key.insert(key.end(), (const char *)&dpmax, (const char *)(&dpmax + 1));
   key.insert(key.end(), (const char *)&pc, (const char *)(&pc + 1));
   key.insert(key.end(), (const char *)&ch, (const char *)(&ch + 1));
+  key.insert(key.end(), (const char *)&xmax, (const char *)(&xmax + 1));
   key.insert(key.end(), (const char *)&qu.progress, (const char *)(&qu.progress + 1));
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {

@@ -9,4 +9,5 @@
 #define GPK_HMC_CHAIN_BYTES hmc_chain_bytes_f32
 #define GPK_HMC_RESET hmc_reset_f32
 #define GPK_HMC_CHECK hmc_check_f32
+#define GPK_XM 1
 #include "hmc_kernels.inc"

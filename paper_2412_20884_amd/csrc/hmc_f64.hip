@@ -9,4 +9,5 @@
 #define GPK_HMC_CHAIN_BYTES hmc_chain_bytes_f64
 #define GPK_HMC_RESET hmc_reset_f64
 #define GPK_HMC_CHECK hmc_check_f64
+#define GPK_XM 0
 #include "hmc_kernels.inc"

@@ -26,7 +26,8 @@ def phi_exact(X, th, kind, xi):
     return solve_triangular(L.T, xi, lower=False)
 
 
-def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None, precond=None):
+def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None, precond=None,
+        prec=None):
     """insts: list of dict(X, y, theta, phi[chains], pi[chains], x0[chains])."""
     ns = [len(b["y"]) for b in insts]
     offs = np.cumsum([0] + ns[:-1])
@@ -44,7 +45,7 @@ def run(insts, kind, dtype, chains, n_steps, dt, tol, mode, maxit=4000, u=None, 
     ud = None if u is None else to_dev(u, torch.float64)
     res = gpk.hmc_leapfrog(Xd, to_dev(y, dtype), to_dev(phi, dtype), thd, pid, xd, kind, ns, offs,
                            chains, d=ds, x_offsets=xoffs, u=ud, n_steps=n_steps, dt=dt,
-                           cg_tol=tol, cg_maxit=maxit, mode=mode, precond=precond)
+                           cg_tol=tol, cg_maxit=maxit, mode=mode, precond=precond, prec=prec)
     torch.cuda.synchronize()
     out = {k: (v.cpu().numpy() if v.dtype == torch.int32 else host(v))
            for k, v in res.items() if v is not None}
@@ -193,26 +194,69 @@ def test_graph_replays_match_batched_bitwise():
             np.testing.assert_array_equal(x, z)
 
 
-def test_bf16x_plain_trajectory():
-    """GP_BF16X trajectories (plain mode, products on the cross-term kernel) against the FP64
-    oracle: the kernel values carry ~1e-4 relative error, so the 4-step trajectory agrees to
-    ~1e-5 in theta and ~1e-4 relative in the energies."""
-    p = I.ard_problem(1500, 20, 23, lo=0.5, hi=4.0, sigma2=0.05)
-    X, y, th = rounded(p["X"], torch.float32), rounded(p["y"], torch.float32), p["theta"]
-    phi = rounded(phi_exact(X, th, "ard", p["xi"]), torch.float32)
-    pi0 = np.random.default_rng(3).normal(size=22) * 0.5
-    Xd = to_dev(X, torch.float32)
-    thd, pid = to_dev(th, torch.float64), to_dev(pi0, torch.float64)
-    xd = torch.zeros(1500, dtype=torch.float32, device=DEV)
-    res = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float32), to_dev(phi, torch.float32), thd, pid, xd,
-                           "ard", [1500], [0], 1, n_steps=4, dt=0.02, cg_tol=1e-6, mode=gpk.PLAIN,
-                           prec="bf16x")
-    torch.cuda.synchronize()
-    th1, pi1 = ohmc.leapfrog(X, "ard", y, phi, th, pi0, 0.02, 4)
-    H1 = ohmc.hamiltonian(X, th1, "ard", y, phi, pi1)
-    assert res["status"].item() == 0
-    assert np.max(np.abs(host(thd) - th1)) < 1e-4
-    assert abs(res["H1"].item() - H1) < 1e-3 * abs(H1)
+@pytest.mark.parametrize("kind,specs", [("ard", [(1500, 20), (777, 40)]), ("iso", [(1111, 3)])])
+def test_bf16x_trajectories_all_modes(kind, specs):
+    """GP_BF16X trajectories on the matrix-core tiles (cross term in bfloat16 hi/lo, everything
+    else in float) in the three modes, against the FP64 oracle, to the precision's 3e-3 budget:
+    the displacements theta_1 - theta_0 and pi_1 - pi_0 of 4 steps, and both energies, within
+    3e-3 of their size (the kernel values' relative error, a few eps32 |x~|^2, reaches the solves
+    amplified by the condition number: ~1e-5 in the force at d = 20, ~5e-4 for the isotropic
+    d = 3 problem, whose near pairs make A ill-conditioned).  Instances of different d
+    (cross-term widths 32 and 64) and ragged N (not multiples of the 32-column tiles, the 64-row
+    stage blocks or the 128-row product blocks) share one persistent launch; its graph replay
+    equals it bit for bit, and the plain mode runs the same tiles one job at a time."""
+    chains = 2
+    insts = []
+    for s, (n, d) in enumerate(specs):
+        if kind == "ard":
+            p = I.ard_problem(n, d, 23 + s, lo=0.5, hi=4.0, sigma2=0.05)
+        else:
+            p = I.iso_problem(n, d, 23 + s, ell=0.3, sigma2=0.05)
+        X, y = rounded(p["X"], torch.float32), rounded(p["y"], torch.float32)
+        g = np.random.default_rng(100 + s)
+        phis = [rounded(phi_exact(X, p["theta"], kind, g.normal(size=n)), torch.float32)
+                for _ in range(chains)]
+        pis = [g.normal(size=len(p["theta"])) * 0.5 for _ in range(chains)]
+        insts.append({"X": X, "y": y, "theta": p["theta"], "phi": phis, "pi": pis,
+                      "x0": [np.zeros(n)] * chains})
+    steps, dt = 4, 0.02
+    outs = {mode: run(insts, kind, torch.float32, chains, steps, dt, 1e-6, mode, prec="bf16x")
+            for mode in (gpk.PLAIN, gpk.BATCHED, gpk.GRAPH)}
+    for key in ("theta", "pi", "H0", "H1", "x", "accepted", "status"):
+        np.testing.assert_array_equal(outs[gpk.BATCHED][key], outs[gpk.GRAPH][key])
+    for key in ("theta", "pi"):
+        np.testing.assert_allclose(outs[gpk.PLAIN][key], outs[gpk.BATCHED][key], rtol=0, atol=1e-6)
+    r = outs[gpk.BATCHED]
+    pos = c = 0
+    for b in insts:
+        nth = len(b["theta"])
+        for h in range(chains):
+            th1, pi1 = ohmc.leapfrog(b["X"], kind, b["y"], b["phi"][h], b["theta"], b["pi"][h], dt,
+                                     steps)
+            H0 = ohmc.hamiltonian(b["X"], b["theta"], kind, b["y"], b["phi"][h], b["pi"][h])
+            H1 = ohmc.hamiltonian(b["X"], th1, kind, b["y"], b["phi"][h], pi1)
+            assert r["status"][c] == 0
+            dth = np.max(np.abs(th1 - b["theta"]))
+            dpi = np.max(np.abs(pi1 - b["pi"][h]))
+            assert np.max(np.abs(r["theta"][pos:pos + nth] - th1)) < 3e-3 * dth
+            assert np.max(np.abs(r["pi"][pos:pos + nth] - pi1)) < 3e-3 * dpi
+            assert abs(r["H0"][c] - H0) < 3e-3 * abs(H0)
+            assert abs(r["H1"][c] - H1) < 3e-3 * abs(H1)
+            pos += nth
+            c += 1
+
+
+def test_bf16x_rejects_cheb_and_precond():
+    """GP_BF16X trajectories take the SE kernels without a preconditioner."""
+    p = I.ard_problem(300, 3, 5, sigma2=0.05)
+    Xd = to_dev(p["X"], torch.float32)
+    yd = to_dev(p["y"], torch.float32)
+    phid = to_dev(p["xi"], torch.float32)
+    thd = to_dev(p["theta"], torch.float64)
+    pid = torch.zeros(5, dtype=torch.float64, device=DEV)
+    xd = torch.zeros(300, dtype=torch.float32, device=DEV)
+    U = torch.zeros(300, 4, dtype=torch.float32, device=DEV)
+    lam = torch.ones(1, 4, dtype=torch.float64, device=DEV)
     with pytest.raises(gpk.GpkError):
-        gpk.hmc_leapfrog(Xd, to_dev(y, torch.float32), to_dev(phi, torch.float32), thd, pid, xd,
-                         "ard", [1500], [0], 1, n_steps=1, mode=gpk.BATCHED, prec="bf16x")
+        gpk.hmc_leapfrog(Xd, yd, phid, thd, pid, xd, "ard", [300], [0], 1, n_steps=1,
+                         mode=gpk.BATCHED, prec="bf16x", precond=(U, lam))
