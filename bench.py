@@ -210,8 +210,22 @@ def cpu_baseline(budget_s=15.0, gpu_res=None):
                                     "workload": "N=1024, d=2, one chain, 100 leapfrog steps of 1e-2"}}
 
 
+def trajectory_tune_entries():
+    """The trajectory entries (op 2) of the library's tuning table, as saved."""
+    import json
+    import tempfile
+
+    from paper_2412_20884_amd import gpk
+
+    with tempfile.NamedTemporaryFile("r", suffix=".json") as f:
+        gpk.tune_save(f.name)
+        entries = json.load(open(f.name))["entries"]
+    keep = ("dp", "rb", "nb", "waves", "cpt_lo", "cpt_hi", "ms")
+    return [{k: e[k] for k in keep} | {"prec": e["prec"]} for e in entries if e["op"] == 2]
+
+
 def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0, rwm=True,
-                   precond_rank=128):
+                   precond_rank=128, tune=True):
     """Chain-leapfrog-steps/s on the batched workload, batched (graph replay) vs plain.
 
     subset = k takes every k-th instance (k = 1: all 64 instances). group = g > 0 runs the
@@ -264,6 +278,16 @@ def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0,
     out = {}
     ref_theta = None
     U_all = lam_all = None
+    if tune:
+        # the trajectory launch (register allocation, columns per trip) for this batch's class,
+        # with and without the preconditioned variant
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gpk.tune_hmc("ard", ns, C, ds)
+        if "graph_nystrom" in modes:
+            gpk.tune_hmc("ard", ns, C, ds, precond_rank=precond_rank)
+        out["autotune"] = {"seconds": time.perf_counter() - t0, "chosen": trajectory_tune_entries()}
+        log(f"leapfrog autotune: {out['autotune']}")
     if "graph_nystrom" in modes:
         Us, lams = [], []
         torch.cuda.synchronize()

@@ -80,6 +80,7 @@ struct HmcChain {
   double centre[kMaxD];
   // schedule
   int n_rb, n_cs, n_jobs;
+  int cpt;  // columns per trip of the product jobs (0: the default for the chain's d)
   int64_t col_chunk;
   // state
   int job;       // job being run by the tiles
@@ -103,6 +104,19 @@ struct HmcChain {
   float *nrm;
   double cscale[kMaxD];  // per-dimension coordinate scale of the theta being solved at
 };
+
+// Waves per SIMD the persistent trajectory kernel is compiled for.  The default: in float the
+// tile variants up to d = 8 fit 128 VGPRs (4 waves) and those up to d = 16 fit 168 with a few
+// spills (3 waves), which the batched leapfrog measures faster than 2 waves without spills; the
+// GP_BF16X jobs (xm != 0) need ~245 VGPRs inside the persistent loop, where 2 waves without spills
+// measure faster than 3 with them.  Each launch also has the alternative instantiation, which the
+// trajectory autotuner can choose.
+constexpr int hmc_waves_default(bool f32, int dpmax, int xm) {
+  return xm ? 2 : (!f32 ? 1 : (dpmax <= 8 ? 4 : (dpmax <= 16 ? 3 : 1)));
+}
+constexpr int hmc_waves_alt(bool f32, int dpmax, int xm) {
+  return xm ? 3 : (!f32 ? 2 : (dpmax <= 8 ? 3 : (dpmax <= 16 ? 2 : 2)));
+}
 
 struct HmcRunParams {
   int n_steps;

@@ -11,6 +11,7 @@
 
 #include "gpk.h"
 #include "hmc.h"
+#include "tune.h"
 
 namespace gpk {
 
@@ -27,15 +28,24 @@ hipError_t hmc_epilogue_f64(void *, const HmcRunParams &, int, hipStream_t);
 hipError_t hmc_gather_f32(void *, int, int, hipStream_t);
 hipError_t hmc_gather_f64(void *, int, int, hipStream_t);
 hipError_t hmc_persistent_f32(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, int, int, hipStream_t);
+                              int, int, int, int, int, hipStream_t);
 hipError_t hmc_persistent_f64(void *, int, const HmcRunParams &, const HmcQueue &, int, long long,
-                              int, int, int, int, hipStream_t);
+                              int, int, int, int, int, hipStream_t);
 hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
 hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
 hipError_t hmc_check_f32(void *, int, hipStream_t);
 hipError_t hmc_check_f64(void *, int, hipStream_t);
 
 namespace {
+
+// Launch configuration of the batched and graph modes: waves per SIMD of the persistent kernel
+// (0: hmc_waves_default) and the product jobs' columns per trip for chains with padded d <= 8
+// and above (0: the default of the tile).  The autotuner forces one on its own thread while it
+// times the candidates; otherwise the tuning table's entry for the batch's class, if any.
+struct LaunchCfg {
+  int waves = 0, cpt_lo = 0, cpt_hi = 0;
+};
+thread_local const LaunchCfg *tl_force = nullptr;
 
 struct InstInfo {
   int64_t n, off, xoff;
@@ -216,7 +226,8 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
                  char *ws, const gp_hmc_params *p,
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
-                 int32_t *status, int32_t *iters, int prec, std::vector<HmcChain<T>> &out) {
+                 int32_t *status, int32_t *iters, int prec, const LaunchCfg &cfg,
+                 std::vector<HmcChain<T>> &out) {
   out.assign(inst.size() * chains, HmcChain<T>());
   int64_t tofs = 0;
   int c = 0;
@@ -284,6 +295,7 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
       ch.ncheb = kind == GP_SE_CHEB ? n_cheb : 0;
       ch.n_rb = L.n_rb[c];
       ch.n_cs = L.n_cs[c];
+      ch.cpt = in.dp <= 8 ? cfg.cpt_lo : cfg.cpt_hi;
       ch.n_jobs = ch.n_rb * ch.n_cs;
       ch.col_chunk = (n + ch.n_cs - 1) / ch.n_cs;
       if (ch.n_cs > 1) {
@@ -310,6 +322,27 @@ struct GraphEntry {
 std::mutex g_mu;
 std::map<void *, std::vector<char>> g_uploaded;  // ws -> descriptor bytes last uploaded
 std::map<void *, GraphEntry> g_graphs;           // ws -> captured trajectory
+
+// Class of a batch in the tuning table: precision, kind, largest padded d, kernel variant and
+// floor(log2) of the largest instance.
+TuneKey traj_key(const gp_kernel *k, const std::vector<InstInfo> &inst, int pc) {
+  TuneKey key;
+  key.op = 2;
+  key.prec = k->prec;
+  key.kind = k->kind;
+  int dpmax = 4;
+  int64_t nmax = 1;
+  for (const InstInfo &in : inst) {
+    dpmax = std::max(dpmax, in.dp);
+    nmax = std::max(nmax, in.n);
+  }
+  key.dp = dpmax;
+  key.rb = (pc ? 1 : 0) | (k->kind == GP_SE_CHEB ? 2 : 0) | (k->prec == GP_BF16X ? 4 : 0);
+  int nb = 0;
+  while (((int64_t)1 << (nb + 1)) <= nmax) ++nb;
+  key.nb = nb;
+  return key;
+}
 
 }  // namespace
 }  // namespace gpk
@@ -344,17 +377,30 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
                 ws ? ws_bytes : (size_t)0);
   const int nc = (int)inst.size() * chains;
   char *w = (char *)ws;
+  const int pc = p->precond_rank > 0 ? 1 : 0;
+
+  LaunchCfg cfg;
+  if (tl_force) {
+    cfg = *tl_force;
+  } else {
+    TuneCfg tc;
+    if (tune_lookup(traj_key(k, inst, pc), &tc)) {
+      cfg.waves = tc.waves;
+      cfg.cpt_lo = tc.cpt_lo;
+      cfg.cpt_hi = tc.cpt_hi;
+    }
+  }
 
   std::vector<char> desc;
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
     fill_chains<double>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                        accepted, status, cg_iters, k->prec, v);
+                        accepted, status, cg_iters, k->prec, cfg, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
     fill_chains<float>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                       accepted, status, cg_iters, k->prec, v);
+                       accepted, status, cg_iters, k->prec, cfg, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
   // chain order for the batched scheduler: largest problems first
@@ -408,7 +454,6 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   qu.progress = p->progress;
   void *chains_dev = w + L.chains;
   const bool f64 = k->prec == GP_F64;
-  const int pc = p->precond_rank > 0 ? 1 : 0;
   const int ch = k->kind == GP_SE_CHEB ? 1 : 0;
   const size_t cb = chain_bytes(k->prec);
 
@@ -465,9 +510,11 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   }
   int64_t total_jobs = 0;
   for (int c = 0; c < nc; ++c) total_jobs += (int64_t)L.n_rb[c] * L.n_cs[c];
-  // as many workgroups as can be resident: 4 per CU, 2 for the GP_BF16X tiles (two 32 KB tile
-  // buffers each)
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * (xmax ? 2 : 4), total_jobs));
+  // the register allocation of the launch (waves per SIMD) and as many workgroups as can be
+  // resident with it: one wave per SIMD each, so `waves` workgroups per CU
+  const int w_def = hmc_waves_default(!f64, dpmax, xmax);
+  const int waves = cfg.waves == hmc_waves_alt(!f64, dpmax, xmax) ? cfg.waves : w_def;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * waves, total_jobs));
   // an idle workgroup gives up after 20 s without claimable work
   const long long idle_limit = (long long)clk_khz * 1000LL * 20LL;
 
@@ -477,8 +524,9 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
             : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, 0, s)
-            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, xmax, s);
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, 0, waves, s)
+            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, xmax,
+                                 waves, s);
     if (r != hipSuccess) return r;
     return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
   };
@@ -496,6 +544,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   key.insert(key.end(), (const char *)&pc, (const char *)(&pc + 1));
   key.insert(key.end(), (const char *)&ch, (const char *)(&ch + 1));
   key.insert(key.end(), (const char *)&xmax, (const char *)(&xmax + 1));
+  key.insert(key.end(), (const char *)&waves, (const char *)(&waves + 1));
   key.insert(key.end(), (const char *)&qu.progress, (const char *)(&qu.progress + 1));
   GraphEntry &ge = g_graphs[ws];
   if (!ge.exec || ge.key != key) {
@@ -548,5 +597,245 @@ gp_status gp_rwm(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, 
   clear_error();
   return run_chains(k, p, b, X, y, phi, theta, xi, x_warm, u_accept, U0, U1, accepted, status,
                     cg_iters, ws, ws_bytes, stream, 1);
+}
+}  // extern "C"
+
+// ---- autotuning of the trajectory launch ---------------------------------------------------
+
+namespace gpk {
+namespace {
+
+// Tuning workspace: the trajectory workspace of the tuning run, then its synthetic inputs.
+struct TuneLayout {
+  size_t hmc, X, y, phi, xw, th, pi, H, ints, U, lam, total;
+  int64_t nrows, nx, nth;
+};
+
+gp_hmc_params tune_params(const gp_hmc_params *p) {
+  gp_hmc_params q;
+  memset(&q, 0, sizeof(q));
+  q.n_steps = 1;
+  q.dt = 0.0;          // theta stays put: every candidate runs the same jobs
+  q.cg_tol = 1e-300;   // every solve runs cg_maxit iterations
+  q.cg_maxit = 4;
+  q.mode = GP_HMC_BATCHED;
+  q.precond_rank = p->precond_rank;
+  return q;
+}
+
+TuneLayout tune_layout(const gp_kernel *k, const gp_hmc_params *q, const gp_batch *b,
+                       const std::vector<InstInfo> &inst) {
+  TuneLayout t;
+  const size_t es = k->prec == GP_F64 ? 8 : 4;
+  const int chains = b->chains_per_inst;
+  t.nrows = t.nx = t.nth = 0;
+  for (const InstInfo &in : inst) {
+    t.nrows += in.n;
+    t.nx += in.n * in.d;
+    t.nth += in.nth;
+  }
+  const int64_t nc = (int64_t)inst.size() * chains;
+  size_t o = 0;
+  t.hmc = o;
+  o += align256(make_layout(inst, chains, k->prec, q->mode, k->kind, k->n_cheb, q->precond_rank).total);
+  t.X = o;
+  o += align256(es * t.nx);
+  t.y = o;
+  o += align256(es * t.nrows);
+  t.phi = o;
+  o += align256(es * t.nrows * chains);
+  t.xw = o;
+  o += align256(es * t.nrows * chains);
+  t.th = o;
+  o += align256(8 * t.nth * chains);
+  t.pi = o;
+  o += align256(8 * t.nth * chains);
+  t.H = o;
+  o += align256(8 * 2 * nc);
+  t.ints = o;
+  o += align256(4 * 3 * nc);
+  t.U = o;
+  o += align256(es * t.nrows * q->precond_rank);
+  t.lam = o;
+  o += align256(8 * inst.size() * q->precond_rank);
+  t.total = o;
+  return t;
+}
+
+template <typename T>
+__global__ void tune_fill(T *a, int64_t m, float lo, float hi, uint64_t salt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  uint64_t z = ((uint64_t)e + salt) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  a[e] = (T)(lo + (hi - lo) * (float)((z >> 40) * (1.0 / 16777216.0)));
+}
+
+template <typename T>
+hipError_t tune_fill_launch(void *a, int64_t m, float lo, float hi, uint64_t salt, hipStream_t s) {
+  if (m < 1) return hipSuccess;
+  tune_fill<T><<<(unsigned)((m + 255) / 256), 256, 0, s>>>((T *)a, m, lo, hi, salt);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace gpk
+
+extern "C" {
+
+size_t gp_tune_hmc_workspace_size(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b) {
+  std::vector<InstInfo> inst;
+  if (!p || collect(k, p, b, inst) != GP_OK) return 0;
+  const gp_hmc_params q = tune_params(p);
+  return tune_layout(k, &q, b, inst).total;
+}
+
+gp_status gp_tune_hmc(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, void *ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  std::vector<InstInfo> inst;
+  gp_status st = collect(k, p, b, inst);
+  if (st) return st;
+  const gp_hmc_params q = tune_params(p);
+  const TuneLayout t = tune_layout(k, &q, b, inst);
+  if (!ws || ws_bytes < t.total)
+    return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", t.total,
+                ws ? ws_bytes : (size_t)0);
+  const bool f64 = k->prec == GP_F64;
+  const int chains = b->chains_per_inst;
+  const int n_inst = (int)inst.size();
+  const int nc = n_inst * chains;
+  char *w = (char *)ws;
+  // synthetic inputs packed instance after instance
+  std::vector<int64_t> npts(n_inst), offs(n_inst), xoffs(n_inst);
+  std::vector<int32_t> dims(n_inst);
+  std::vector<double> th0;
+  int64_t ro = 0, xo = 0;
+  int dpmax = 4, xmax = 0, any_lo = 0, any_hi = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    npts[i] = inst[i].n;
+    offs[i] = ro;
+    xoffs[i] = xo;
+    dims[i] = inst[i].d;
+    ro += inst[i].n;
+    xo += inst[i].n * inst[i].d;
+    dpmax = std::max(dpmax, inst[i].dp);
+    xmax = std::max(xmax, xm_width(k->prec, inst[i].d));
+    (inst[i].dp <= 8 ? any_lo : any_hi) = 1;
+    for (int h = 0; h < chains; ++h)
+      for (int j = 0; j < inst[i].nth; ++j)
+        th0.push_back(j == inst[i].nth - 1 ? std::log(0.1) : (j == 0 ? 0.0 : std::log(0.5)));
+  }
+  if (k->kind == GP_SE_CHEB)  // Theta = 0 (unit amplitude), log l = log 0.5
+    for (size_t j = 0, c = 0; c < (size_t)nc; ++c) {
+      const int nth = inst[c / chains].nth;
+      for (int q2 = 0; q2 < nth - 2; ++q2) th0[j + q2] = 0.0;
+      j += nth;
+    }
+  gp_batch sb = *b;
+  sb.n_points = npts.data();
+  sb.offsets = offs.data();
+  sb.x_offsets = xoffs.data();
+  sb.d = dims.data();
+  gp_hmc_params qq = q;
+  if (q.precond_rank > 0) {
+    qq.precond_U = w + t.U;
+    qq.precond_lam = (const double *)(w + t.lam);
+  }
+  hipError_t e = hipSuccess;
+  const int64_t rows = t.nrows;
+  auto fill = [&](size_t off, int64_t m, float lo, float hi, uint64_t salt) {
+    if (e != hipSuccess) return;
+    e = f64 ? tune_fill_launch<double>(w + off, m, lo, hi, salt, stream)
+            : tune_fill_launch<float>(w + off, m, lo, hi, salt, stream);
+  };
+  fill(t.X, t.nx, 0.f, 1.f, 11);
+  fill(t.y, rows, -1.f, 1.f, 12);
+  fill(t.phi, rows * chains, -1.f, 1.f, 13);
+  if (e == hipSuccess) e = hipMemsetAsync(w + t.U, 0, (f64 ? 8 : 4) * rows * q.precond_rank, stream);
+  if (e != hipSuccess) return hip_fail(e, "tuner inputs");
+  std::vector<double> lam((size_t)n_inst * q.precond_rank, 1.0);
+  if (!lam.empty()) {
+    e = hipMemcpyAsync(w + t.lam, lam.data(), 8 * lam.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "tuner inputs");
+  }
+  // candidates: the two register allocations, and columns per trip where such chains exist
+  std::vector<LaunchCfg> cands;
+  const int wopt[2] = {hmc_waves_default(!f64, dpmax, xmax), hmc_waves_alt(!f64, dpmax, xmax)};
+  const std::vector<int> lo_opt = (any_lo && !xmax) ? std::vector<int>{4, 2} : std::vector<int>{0};
+  const std::vector<int> hi_opt = (any_hi && !xmax) ? std::vector<int>{2, 1} : std::vector<int>{0};
+  for (int wv : wopt)
+    for (int cl : lo_opt)
+      for (int chh : hi_opt) {
+        LaunchCfg c;
+        c.waves = wv;
+        c.cpt_lo = cl;
+        c.cpt_hi = chh;
+        cands.push_back(c);
+      }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "tuner events");
+  }
+  const size_t es = f64 ? 8 : 4;
+  char *X = w + t.X, *y = w + t.y, *phi = w + t.phi, *xw = w + t.xw;
+  double *th = (double *)(w + t.th), *pi = (double *)(w + t.pi), *H = (double *)(w + t.H);
+  int32_t *ints = (int32_t *)(w + t.ints);
+  const size_t hmc_bytes = t.X - t.hmc;
+  TuneCfg best;
+  best.splits = 1;
+  best.ib = 1;
+  best.ms = 1e30f;
+  for (const LaunchCfg &c : cands) {
+    tl_force = &c;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3 && st == GP_OK && e == hipSuccess; ++rep) {
+      // the same start for every run: theta, pi = 0 and x = 0
+      e = hipMemcpyAsync(th, th0.data(), 8 * th0.size(), hipMemcpyHostToDevice, stream);
+      if (e == hipSuccess) e = hipMemsetAsync(pi, 0, 8 * th0.size(), stream);
+      if (e == hipSuccess) e = hipMemsetAsync(xw, 0, es * rows * chains, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, stream);
+      if (e != hipSuccess) break;
+      st = run_chains(k, &qq, &sb, X, y, phi, th, pi, xw, nullptr, H, H + nc, ints, ints + nc,
+                      ints + 2 * nc, w + t.hmc, hmc_bytes, stream, 0);
+      if (st != GP_OK) break;
+      e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run uploads descriptors
+    }
+    tl_force = nullptr;
+    if (st != GP_OK || e != hipSuccess) break;
+    if (ms_min < best.ms) {
+      best.ms = ms_min;
+      best.waves = c.waves;
+      best.cpt_lo = c.cpt_lo;
+      best.cpt_hi = c.cpt_hi;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    // the tuning workspace belongs to the caller again: forget its descriptors and graph
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_uploaded.erase(w + t.hmc);
+    auto itg = g_graphs.find(w + t.hmc);
+    if (itg != g_graphs.end()) {
+      if (itg->second.exec) (void)hipGraphExecDestroy(itg->second.exec);
+      g_graphs.erase(itg);
+    }
+  }
+  if (st != GP_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "tuner timing");
+  tune_store(traj_key(k, inst, q.precond_rank > 0 ? 1 : 0), best);
+  return GP_OK;
 }
 }  // extern "C"

@@ -50,6 +50,19 @@ __global__ void synth_theta(double *th, int nth, double log_ell) {
   if (k < nth) th[k] = (k == 0) ? 0.0 : (k == nth - 1 ? -4.605170185988091 : log_ell);
 }
 
+// One table line (the format gp_tune_save writes); trajectory entries carry three more fields.
+bool parse_entry(const char *line, TuneKey *k, TuneCfg *c) {
+  int n = sscanf(line, " {\"op\": %d, \"prec\": %d, \"kind\": %d, \"dp\": %d, \"rb\": %d, "
+                       "\"nb\": %d, \"splits\": %d, \"ib\": %d, \"ms\": %f, \"waves\": %d, "
+                       "\"cpt_lo\": %d, \"cpt_hi\": %d}",
+                 &k->op, &k->prec, &k->kind, &k->dp, &k->rb, &k->nb, &c->splits, &c->ib, &c->ms,
+                 &c->waves, &c->cpt_lo, &c->cpt_hi);
+  if (n < 9) return false;
+  if (n < 12) c->waves = c->cpt_lo = c->cpt_hi = 0;
+  if (k->op == 2) return c->waves >= 1 && c->waves <= 4;
+  return c->splits >= 1 && (c->ib == 1 || c->ib == 2);
+}
+
 void load_env_once() {
   if (g_env_loaded) return;
   g_env_loaded = true;
@@ -61,10 +74,7 @@ void load_env_once() {
   while (fgets(line, sizeof(line), f)) {
     TuneKey k;
     TuneCfg c;
-    if (sscanf(line, " {\"op\": %d, \"prec\": %d, \"kind\": %d, \"dp\": %d, \"rb\": %d, \"nb\": %d, "
-                     "\"splits\": %d, \"ib\": %d, \"ms\": %f}",
-               &k.op, &k.prec, &k.kind, &k.dp, &k.rb, &k.nb, &c.splits, &c.ib, &c.ms) == 9)
-      g_table[as_tuple(k)] = c;
+    if (parse_entry(line, &k, &c)) g_table[as_tuple(k)] = c;
   }
   fclose(f);
 }
@@ -222,9 +232,11 @@ gp_status gp_tune_save(const char *path) {
     const auto &t = kv.first;
     const TuneCfg &c = kv.second;
     fprintf(f, " {\"op\": %d, \"prec\": %d, \"kind\": %d, \"dp\": %d, \"rb\": %d, \"nb\": %d, "
-               "\"splits\": %d, \"ib\": %d, \"ms\": %.6f}%s\n",
+               "\"splits\": %d, \"ib\": %d, \"ms\": %.6f, \"waves\": %d, \"cpt_lo\": %d, "
+               "\"cpt_hi\": %d}%s\n",
             std::get<0>(t), std::get<1>(t), std::get<2>(t), std::get<3>(t), std::get<4>(t),
-            std::get<5>(t), c.splits, c.ib, c.ms, ++i < g_table.size() ? "," : "");
+            std::get<5>(t), c.splits, c.ib, c.ms, c.waves, c.cpt_lo, c.cpt_hi,
+            ++i < g_table.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -243,10 +255,7 @@ gp_status gp_tune_load(const char *path) {
   while (fgets(line, sizeof(line), f)) {
     TuneKey k;
     TuneCfg c;
-    if (sscanf(line, " {\"op\": %d, \"prec\": %d, \"kind\": %d, \"dp\": %d, \"rb\": %d, \"nb\": %d, "
-                     "\"splits\": %d, \"ib\": %d, \"ms\": %f}",
-               &k.op, &k.prec, &k.kind, &k.dp, &k.rb, &k.nb, &c.splits, &c.ib, &c.ms) == 9) {
-      if (c.splits < 1 || (c.ib != 1 && c.ib != 2)) continue;
+    if (parse_entry(line, &k, &c)) {
       g_table[as_tuple(k)] = c;
       ++got;
     }

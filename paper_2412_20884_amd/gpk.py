@@ -28,7 +28,7 @@ EXPORTED = (
     "gp_tune_products", "gp_tune_save", "gp_tune_load", "gp_tune_entries", "gp_tune_clear",
     "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
     "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve", "gp_implicit_workspace_size",
-    "gp_hmc_implicit", "gp_rwm", "gp_kmatvec_noalloc",
+    "gp_hmc_implicit", "gp_rwm", "gp_kmatvec_noalloc", "gp_tune_hmc_workspace_size", "gp_tune_hmc",
 )
 
 
@@ -117,6 +117,12 @@ def lib():
     L.gp_tune_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32]
     L.gp_tune_products.restype = _i32
     L.gp_tune_products.argtypes = [ctypes.POINTER(Kernel), _i64, _i32, _i32, _vp, _sz, _vp]
+    L.gp_tune_hmc_workspace_size.restype = _sz
+    L.gp_tune_hmc_workspace_size.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
+                                             ctypes.POINTER(Batch)]
+    L.gp_tune_hmc.restype = _i32
+    L.gp_tune_hmc.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(HmcParams),
+                              ctypes.POINTER(Batch), _vp, _sz, _vp]
     L.gp_tune_save.restype = _i32
     L.gp_tune_save.argtypes = [ctypes.c_char_p]
     L.gp_tune_load.restype = _i32
@@ -519,6 +525,41 @@ def tune(kind, d, n, r, dtype=torch.float32, with_grad=True, device="cuda:0", pr
     ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     _check(lib().gp_tune_products(ctypes.byref(k), int(n), int(r), 1 if with_grad else 0, _p(ws),
                                   nbytes, _stream(torch.device(device))))
+    return int(lib().gp_tune_entries())
+
+
+def tune_hmc(kind, n_points, chains, d, dtype=torch.float32, prec=None, n_cheb=0,
+             precond_rank=0, device="cuda:0"):
+    """Autotune the batched / graph trajectory launch for a batch of this geometry (instances of
+    n_points[i] points in d[i] dimensions, `chains` chains each) on synthetic inputs.  Returns the
+    number of entries in the tuning table."""
+    n_points = [int(v) for v in n_points]
+    dims = [int(v) for v in d]
+    if len(dims) != len(n_points) or not n_points:
+        raise ValueError("n_points and d need one entry per instance")
+    k = Kernel(kind_code(kind), prec_code(dtype, prec), max(dims), 0, int(n_cheb))
+    dev = torch.device(device)
+    keep = []
+    pU = plam = None
+    if precond_rank:
+        # the tuner reads no factor; any valid pointers satisfy the parameter check
+        keep.append(torch.empty(1, dtype=torch.float64, device=dev))
+        pU = plam = _p(keep[0])
+    prm = HmcParams(1, 0.0, 1e-6, 4, BATCHED, None, int(precond_rank), pU, plam, None)
+    npts = (ctypes.c_int64 * len(n_points))(*n_points)
+    offs_l, o = [], 0
+    for v in n_points:
+        offs_l.append(o)
+        o += v
+    offs = (ctypes.c_int64 * len(n_points))(*offs_l)
+    dd = (ctypes.c_int32 * len(dims))(*dims)
+    b = Batch(len(n_points), int(chains), npts, offs, dd, None)
+    nbytes = int(lib().gp_tune_hmc_workspace_size(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b)))
+    if nbytes == 0:
+        _check(lib().gp_tune_hmc(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, 0, None))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _check(lib().gp_tune_hmc(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), _p(ws), nbytes,
+                             _stream(dev)))
     return int(lib().gp_tune_entries())
 
 

@@ -129,6 +129,40 @@ def test_tune_table_json_roundtrip(tmp_path):
     assert L.gp_tune_load(b"/nonexistent/x.json") == 1
 
 
+def test_trajectory_tune_entries_and_validation(tmp_path):
+    # trajectory entries (op 2) carry the launch configuration; a wave count outside 1..4 is
+    # rejected on load
+    gpk.tune_clear()
+    src = tmp_path / "traj.json"
+    src.write_text('{"version": 1, "entries": [\n'
+                   ' {"op": 2, "prec": 1, "kind": 1, "dp": 16, "rb": 0, "nb": 14, "splits": 1, "ib": 1, '
+                   '"ms": 12.5, "waves": 2, "cpt_lo": 4, "cpt_hi": 1},\n'
+                   ' {"op": 2, "prec": 1, "kind": 1, "dp": 8, "rb": 0, "nb": 14, "splits": 1, "ib": 1, '
+                   '"ms": 12.5, "waves": 9, "cpt_lo": 4, "cpt_hi": 1}\n'
+                   ']}\n')
+    gpk.tune_load(src)
+    assert gpk.tune_entries() == 1
+    out = tmp_path / "traj_out.json"
+    gpk.tune_save(out)
+    text = out.read_text()
+    assert '"waves": 2' in text and '"cpt_lo": 4' in text and '"cpt_hi": 1' in text
+    gpk.tune_clear()
+    # validation happens before any HIP call
+    L = gpk.lib()
+    k = gpk.Kernel(gpk.ARD, gpk.F32, 4, 0, 0)
+    prm = gpk.HmcParams(1, 0.0, 1e-6, 4, gpk.BATCHED, None, 0, None, None, None)
+    npts = (ctypes.c_int64 * 2)(1000, 500)
+    offs = (ctypes.c_int64 * 2)(0, 1000)
+    dd = (ctypes.c_int32 * 2)(4, 16)
+    b = gpk.Batch(2, 2, npts, offs, dd, None)
+    nb = L.gp_tune_hmc_workspace_size(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b))
+    assert nb > L.gp_hmc_workspace_size(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b))
+    assert L.gp_tune_hmc(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(b), None, 0, None) == 4
+    bad = gpk.Batch(2, 0, npts, offs, dd, None)
+    assert L.gp_tune_hmc_workspace_size(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(bad)) == 0
+    assert L.gp_tune_hmc(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(bad), None, 0, None) == 2
+
+
 def test_cheb_workspace_and_tuner():
     L = gpk.lib()
     k = ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 3))
