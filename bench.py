@@ -283,7 +283,8 @@ def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0,
         # with and without the preconditioned variant
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gpk.tune_hmc("ard", ns, C, ds)
+        if any(m != "graph_nystrom" and m != "plain" for m in modes):
+            gpk.tune_hmc("ard", ns, C, ds)
         if "graph_nystrom" in modes:
             gpk.tune_hmc("ard", ns, C, ds, precond_rank=precond_rank)
         out["autotune"] = {"seconds": time.perf_counter() - t0, "chosen": trajectory_tune_entries()}
@@ -950,7 +951,8 @@ def main():
                                           args.leapfrog_precond_rank)
     if not args.no_leapfrog_full:
         # the whole batched workload (64 instances x 8 chains, 20 steps) in one persistent launch,
-        # Nystrom-preconditioned, graph-replayed
+        # Nystrom-preconditioned, graph-replayed, its launch configuration tuned for its own class
+        # (512 chains)
         line["leapfrog_full"] = bench_leapfrog(("graph_nystrom",), 1, 0, False,
                                                args.leapfrog_precond_rank)
     if not args.no_ard8:

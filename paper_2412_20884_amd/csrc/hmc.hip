@@ -324,8 +324,9 @@ std::map<void *, std::vector<char>> g_uploaded;  // ws -> descriptor bytes last 
 std::map<void *, GraphEntry> g_graphs;           // ws -> captured trajectory
 
 // Class of a batch in the tuning table: precision, kind, largest padded d, kernel variant and
-// floor(log2) of the largest instance.
-TuneKey traj_key(const gp_kernel *k, const std::vector<InstInfo> &inst, int pc) {
+// floor(log2) of the number of chains (in rb, above the variant bits), floor(log2) of the
+// largest instance.
+TuneKey traj_key(const gp_kernel *k, const std::vector<InstInfo> &inst, int chains, int pc) {
   TuneKey key;
   key.op = 2;
   key.prec = k->prec;
@@ -337,7 +338,9 @@ TuneKey traj_key(const gp_kernel *k, const std::vector<InstInfo> &inst, int pc) 
     nmax = std::max(nmax, in.n);
   }
   key.dp = dpmax;
-  key.rb = (pc ? 1 : 0) | (k->kind == GP_SE_CHEB ? 2 : 0) | (k->prec == GP_BF16X ? 4 : 0);
+  int cb = 0;
+  while (((int64_t)1 << (cb + 1)) <= (int64_t)inst.size() * chains) ++cb;
+  key.rb = (pc ? 1 : 0) | (k->kind == GP_SE_CHEB ? 2 : 0) | (k->prec == GP_BF16X ? 4 : 0) | (cb << 3);
   int nb = 0;
   while (((int64_t)1 << (nb + 1)) <= nmax) ++nb;
   key.nb = nb;
@@ -384,7 +387,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
     cfg = *tl_force;
   } else {
     TuneCfg tc;
-    if (tune_lookup(traj_key(k, inst, pc), &tc)) {
+    if (tune_lookup(traj_key(k, inst, chains, pc), &tc)) {
       cfg.waves = tc.waves;
       cfg.cpt_lo = tc.cpt_lo;
       cfg.cpt_hi = tc.cpt_hi;
@@ -762,20 +765,11 @@ gp_status gp_tune_hmc(const gp_kernel *k, const gp_hmc_params *p, const gp_batch
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "tuner inputs");
   }
-  // candidates: the two register allocations, and columns per trip where such chains exist
-  std::vector<LaunchCfg> cands;
+  // candidates, one knob at a time from the defaults: the alternative register allocation, then
+  // the other columns per trip for the chains with padded d <= 8, then for those above
   const int wopt[2] = {hmc_waves_default(!f64, dpmax, xmax), hmc_waves_alt(!f64, dpmax, xmax)};
-  const std::vector<int> lo_opt = (any_lo && !xmax) ? std::vector<int>{4, 2} : std::vector<int>{0};
-  const std::vector<int> hi_opt = (any_hi && !xmax) ? std::vector<int>{2, 1} : std::vector<int>{0};
-  for (int wv : wopt)
-    for (int cl : lo_opt)
-      for (int chh : hi_opt) {
-        LaunchCfg c;
-        c.waves = wv;
-        c.cpt_lo = cl;
-        c.cpt_hi = chh;
-        cands.push_back(c);
-      }
+  const int lo_opt[2] = {4, 2}, hi_opt[2] = {2, 1};
+  const int n_knobs = xmax ? 1 : 3;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -788,14 +782,11 @@ gp_status gp_tune_hmc(const gp_kernel *k, const gp_hmc_params *p, const gp_batch
   double *th = (double *)(w + t.th), *pi = (double *)(w + t.pi), *H = (double *)(w + t.H);
   int32_t *ints = (int32_t *)(w + t.ints);
   const size_t hmc_bytes = t.X - t.hmc;
-  TuneCfg best;
-  best.splits = 1;
-  best.ib = 1;
-  best.ms = 1e30f;
-  for (const LaunchCfg &c : cands) {
+  // one timed run of configuration c (after a run that uploads its descriptors)
+  auto time_cfg = [&](const LaunchCfg &c) -> float {
     tl_force = &c;
     float ms_min = 1e30f;
-    for (int rep = 0; rep < 3 && st == GP_OK && e == hipSuccess; ++rep) {
+    for (int rep = 0; rep < 2 && st == GP_OK && e == hipSuccess; ++rep) {
       // the same start for every run: theta, pi = 0 and x = 0
       e = hipMemcpyAsync(th, th0.data(), 8 * th0.size(), hipMemcpyHostToDevice, stream);
       if (e == hipSuccess) e = hipMemsetAsync(pi, 0, 8 * th0.size(), stream);
@@ -810,17 +801,35 @@ gp_status gp_tune_hmc(const gp_kernel *k, const gp_hmc_params *p, const gp_batch
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run uploads descriptors
+      if (rep > 0 && ms < ms_min) ms_min = ms;
     }
     tl_force = nullptr;
-    if (st != GP_OK || e != hipSuccess) break;
-    if (ms_min < best.ms) {
-      best.ms = ms_min;
-      best.waves = c.waves;
-      best.cpt_lo = c.cpt_lo;
-      best.cpt_hi = c.cpt_hi;
+    return ms_min;
+  };
+  LaunchCfg cur;
+  cur.waves = wopt[0];
+  cur.cpt_lo = any_lo && !xmax ? lo_opt[0] : 0;
+  cur.cpt_hi = any_hi && !xmax ? hi_opt[0] : 0;
+  float cur_ms = time_cfg(cur);
+  for (int knob = 0; knob < n_knobs && st == GP_OK && e == hipSuccess; ++knob) {
+    if ((knob == 1 && !any_lo) || (knob == 2 && !any_hi)) continue;
+    LaunchCfg c = cur;
+    if (knob == 0) c.waves = wopt[1];
+    if (knob == 1) c.cpt_lo = lo_opt[1];
+    if (knob == 2) c.cpt_hi = hi_opt[1];
+    const float ms = time_cfg(c);
+    if (ms < cur_ms) {
+      cur = c;
+      cur_ms = ms;
     }
   }
+  TuneCfg best;
+  best.splits = 1;
+  best.ib = 1;
+  best.ms = cur_ms;
+  best.waves = cur.waves;
+  best.cpt_lo = cur.cpt_lo;
+  best.cpt_hi = cur.cpt_hi;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {
@@ -835,7 +844,7 @@ gp_status gp_tune_hmc(const gp_kernel *k, const gp_hmc_params *p, const gp_batch
   }
   if (st != GP_OK) return st;
   if (e != hipSuccess) return hip_fail(e, "tuner timing");
-  tune_store(traj_key(k, inst, q.precond_rank > 0 ? 1 : 0), best);
+  tune_store(traj_key(k, inst, chains, q.precond_rank > 0 ? 1 : 0), best);
   return GP_OK;
 }
 }  // extern "C"
