@@ -108,14 +108,14 @@ struct HmcChain {
 // Waves per SIMD the persistent trajectory kernel is compiled for.  The default: in float the
 // tile variants up to d = 8 fit 128 VGPRs (4 waves) and those up to d = 16 fit 168 with a few
 // spills (3 waves), which the batched leapfrog measures faster than 2 waves without spills; the
-// GP_BF16X jobs (xm != 0) need ~245 VGPRs inside the persistent loop, where 2 waves without spills
-// measure faster than 3 with them.  Each launch also has the alternative instantiation, which the
-// trajectory autotuner can choose.
+// GP_BF16X jobs (xm != 0) run at 3 waves (their spills sit outside the pair loops: 1.01 s
+// against 1.14 s at 2 waves for a 2-step d = 64 trajectory).  Each launch also has the
+// alternative instantiation, which the trajectory autotuner can choose.
 constexpr int hmc_waves_default(bool f32, int dpmax, int xm) {
-  return xm ? 2 : (!f32 ? 1 : (dpmax <= 8 ? 4 : (dpmax <= 16 ? 3 : 1)));
+  return xm ? 3 : (!f32 ? 1 : (dpmax <= 8 ? 4 : (dpmax <= 16 ? 3 : 1)));
 }
 constexpr int hmc_waves_alt(bool f32, int dpmax, int xm) {
-  return xm ? 3 : (!f32 ? 2 : (dpmax <= 8 ? 3 : (dpmax <= 16 ? 2 : 2)));
+  return xm ? 2 : (!f32 ? 2 : (dpmax <= 8 ? 3 : (dpmax <= 16 ? 2 : 2)));
 }
 
 struct HmcRunParams {
