@@ -1,21 +1,25 @@
 """Statistical check of the whole sampler: the pseudofermion HMC chain targets P(theta).
 
 The E1 problem of Section 4.1 (N = 10 points equispaced on [-1, 1), y_i = 1, sigma^2 = 0.1 held
-fixed, the [-3, 3]^2 box of the paper's grid as the prior support) with the isotropic SE kernel's
-(log alpha, log l) free; tests/golden/e1_grid_marginals.json holds the exact marginal CDFs of
-P(theta) on the paper's 100^2 grid (trapezoid rule), written from the oracle's Cholesky posterior.
+fixed, the [-3, 3]^2 box of the paper's grid as the prior support), twice: with the paper's own
+kernel there, the Chebyshev-amplitude SE kernel with N_cheb = 2 coefficients (Theta_0, Theta_1)
+free and 2 l^2 = 1 fixed, and with the isotropic SE kernel's (log alpha, log l) free.
+tests/golden/e1_cheb_grid_marginals.json and e1_grid_marginals.json hold the exact marginal CDFs
+of P(theta) on the paper's 100^2 grid (trapezoid rule), written from the oracle's Cholesky
+posterior.
 
 500 chains (the paper's B) run Algorithm 1 on the device: per update, phi | theta is drawn
 exactly (phi = L^{-T} xi with A = L L^T, on the host), pi ~ N(0, I), and one graph-replayed
 leapfrog trajectory of N_int = 3 steps of 0.4 (the paper's E1 leapfrog settings) with the
-Metropolis decision on the device; the diagonal inverse mass (1, 1, 0) holds sigma^2 fixed, and
-a proposal outside the box is rejected by the caller (the box prior).  Chains start from the grid
-posterior itself (cells drawn from the joint grid density, uniform within a cell) and run 20
-updates before 200 are kept.  The empirical marginal CDFs at the grid nodes must lie within the
-Dvoretzky-Kiefer-Wolfowitz radius sqrt(log(2/delta) / (2 n_eff)), delta = 0.01, of the exact ones,
-with n_eff = B L / tau and tau from the Appendix C estimator on the chain-averaged autocovariance.
-A sampler that targets a different density (a wrong force sign or factor, a wrong energy or a
-wrong accept rule) moves these CDFs by far more than the radius.
+Metropolis decision on the device; the diagonal inverse mass holds the fixed hyperparameters
+still (a zero entry), and a proposal outside the box is rejected by the caller (the box prior).
+Chains start from the grid posterior itself (cells drawn from the joint grid density, uniform
+within a cell) and run 20 updates before 200 are kept.  The empirical marginal CDFs at the grid
+nodes must lie within the Dvoretzky-Kiefer-Wolfowitz radius sqrt(log(2/delta) / (2 n_eff)),
+delta = 0.01, of the exact ones, with n_eff = B L / tau and tau from the Appendix C estimator on
+the chain-averaged autocovariance.  A sampler that targets a different density (a wrong force
+sign or factor, a wrong energy or a wrong accept rule) moves these CDFs by far more than the
+radius.
 """
 import json
 import os
@@ -43,30 +47,40 @@ def _e1():
         sys.path.remove(GOLD)
     spec, X, y, axis = make_golden.e1_data()
     gold = json.load(open(os.path.join(GOLD, "e1_grid_marginals.json")))
-    return spec, X, y, axis, gold
+    gold_cheb = json.load(open(os.path.join(GOLD, "e1_cheb_grid_marginals.json")))
+    return spec, X, y, axis, gold, gold_cheb, make_golden.cheb_base(spec)
 
 
-def test_e1_marginals_within_dkw_radius():
-    spec, X, y, axis, gold = _e1()
+@pytest.mark.parametrize("kind", ["cheb", "iso"])
+def test_e1_marginals_within_dkw_radius(kind):
+    spec, X, y, axis, gold_iso, gold_cheb, cheb_base = _e1()
     n = len(y)
     B, burn, keep = 500, 20, 200
     lo, hi = spec["grid_lo"], spec["grid_hi"]
     ls2 = np.log(spec["sigma2"])
     g = np.random.default_rng([2412, 20884])
+    if kind == "cheb":
+        base, n_cheb = cheb_base, spec["n_cheb"]
+        inv_mass = [1.0, 1.0, 0.0, 0.0]
+        cdf_gold = {0: np.asarray(gold_cheb["cdf_theta0"]), 1: np.asarray(gold_cheb["cdf_theta1"])}
+    else:
+        base, n_cheb = np.array([0.0, 0.0, ls2]), 0
+        inv_mass = [1.0, 1.0, 0.0]
+        cdf_gold = {0: np.asarray(gold_iso["cdf_log_alpha"]), 1: np.asarray(gold_iso["cdf_log_l"])}
+    nt = len(base)
     # start from the grid posterior: joint cell probabilities, uniform jitter within a cell
-    base = np.array([0.0, 0.0, ls2])
-    logp = posterior.grid_log_posterior(X, "iso", y, base, (0, 1), (axis, axis))
+    logp = posterior.grid_log_posterior(X, kind, y, base, (0, 1), (axis, axis))
     pc = np.exp(logp - logp.max()).ravel()
     cell = g.choice(pc.size, size=B, p=pc / pc.sum())
     h = axis[1] - axis[0]
     th0 = np.stack([axis[cell // len(axis)], axis[cell % len(axis)]], 1)
     th0 = np.clip(th0 + g.uniform(-0.5, 0.5, size=(B, 2)) * h, lo, hi)
-    theta = np.concatenate([th0, np.full((B, 1), ls2)], 1)
+    theta = np.concatenate([th0, np.tile(base[2:], (B, 1))], 1)
 
     Xd = to_dev(X, torch.float64)
     yd = to_dev(y, torch.float64)
     thd = to_dev(theta.ravel(), torch.float64)
-    pid = torch.zeros(3 * B, dtype=torch.float64, device=DEV)
+    pid = torch.zeros(nt * B, dtype=torch.float64, device=DEV)
     phid = torch.zeros(B * n, dtype=torch.float64, device=DEV)
     xd = torch.zeros(B * n, dtype=torch.float64, device=DEV)
     ud = torch.zeros(B, dtype=torch.float64, device=DEV)
@@ -74,22 +88,22 @@ def test_e1_marginals_within_dkw_radius():
     acc_total = 0
     r = None  # the first call's outputs are passed back: later graph launches replay the capture
     for it in range(burn + keep):
-        th_host = host(thd).reshape(B, 3)
+        th_host = host(thd).reshape(B, nt)
         phi = np.empty((B, n))
         for b in range(B):
-            Lc = np.linalg.cholesky(ogp.a_matrix(X, th_host[b], "iso"))
+            Lc = np.linalg.cholesky(ogp.a_matrix(X, th_host[b], kind))
             phi[b] = np.linalg.solve(Lc.T, g.standard_normal(n))
         phid.copy_(torch.from_numpy(phi.ravel()))
-        pid.copy_(torch.from_numpy(g.standard_normal(3 * B)))
+        pid.copy_(torch.from_numpy(g.standard_normal(nt * B)))
         ud.copy_(torch.from_numpy(g.uniform(size=B)))
-        r = gpk.hmc_leapfrog(Xd, yd, phid, thd, pid, xd, "iso", [n], [0], B, u=ud, n_steps=3,
+        r = gpk.hmc_leapfrog(Xd, yd, phid, thd, pid, xd, kind, [n], [0], B, u=ud, n_steps=3,
                              dt=0.4, cg_tol=1e-10, cg_maxit=200, mode=gpk.GRAPH,
-                             inv_mass=[1.0, 1.0, 0.0], outputs=r)
+                             inv_mass=inv_mass, n_cheb=n_cheb, outputs=r)
         torch.cuda.synchronize()
         st = r["status"].cpu().numpy()
         assert np.all(st == 0), np.unique(st)
-        th_new = host(thd).reshape(B, 3)
-        assert np.all(th_new[:, 2] == ls2)  # sigma^2 never moves
+        th_new = host(thd).reshape(B, nt)
+        assert np.all(th_new[:, 2:] == base[2:])  # the fixed hyperparameters never move
         # the box prior: a proposal outside [-3, 3]^2 is rejected
         out = np.any((th_new[:, :2] < lo) | (th_new[:, :2] > hi), axis=1)
         th_new[out] = th_host[out]
@@ -99,7 +113,6 @@ def test_e1_marginals_within_dkw_radius():
             samples[it - burn] = th_new[:, :2]
             acc_total += int(acc.sum())
     rate = acc_total / (B * keep)
-    cdf_gold = {0: np.asarray(gold["cdf_log_alpha"]), 1: np.asarray(gold["cdf_log_l"])}
     report = []
     for k in (0, 1):
         tau = stats.iat_chains(samples[:, :, k].T, max_lag=100)
@@ -109,7 +122,7 @@ def test_e1_marginals_within_dkw_radius():
         emp = np.searchsorted(s, axis, side="right") / s.size
         err = float(np.max(np.abs(emp - cdf_gold[k])))
         report.append((k, tau, n_eff, radius, err))
-        print(f"E1 component {k}: tau {tau:.2f}, n_eff {n_eff:.0f}, sup CDF error {err:.4f}, "
+        print(f"E1 {kind} component {k}: tau {tau:.2f}, n_eff {n_eff:.0f}, sup CDF error {err:.4f}, "
               f"DKW radius {radius:.4f}, acceptance {rate:.3f}")
     assert 0.3 < rate < 0.98
     for k, tau, n_eff, radius, err in report:
