@@ -340,7 +340,8 @@ gp_status gp_pole_weights(double m, double M, int32_t n_poles, double *w, double
 
 enum {
   GP_PHI_CG_MAXIT = 1,  /* some shifted system had not reached tol after maxit iterations */
-  GP_PHI_NONFINITE = 2  /* a NaN or infinity appeared (or A p . p <= 0): phi is not usable */
+  GP_PHI_NONFINITE = 2, /* a NaN or infinity appeared (or A p . p <= 0): phi is not usable */
+  GP_PHI_ABORTED = 4    /* gp_phi_refresh_chains: the scheduler stopped before the chain finished */
 };
 
 typedef struct {
@@ -383,6 +384,40 @@ gp_status gp_phi_refresh(const gp_kernel *k, const gp_phi_params *p, int64_t n, 
                          const double *theta, int32_t r, const void *xi, int64_t ldxi, void *phi,
                          int64_t ldphi, int32_t *status, int32_t *iters, double *bounds, void *ws,
                          size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace gp_phi_refresh_chains needs; 0 for an invalid description. */
+size_t gp_phi_chains_workspace_size(const gp_kernel *k, const gp_phi_params *p, int32_t mode,
+                                    const gp_batch *b);
+
+/*
+ * gp_phi_refresh_chains -- the Gibbs step phi | theta of Algorithm 1 for every chain of a batch,
+ * each at its own theta: phi_c = A(theta_c)^{-1/2} xi_c by the pole expansion of Section 3.1
+ * (eq. pex) with the weights and shifts of Appendix A (eq. msqdisc), all shifted systems of a
+ * chain solved by multi-shift CG on A(theta_c).  The chains run as the trajectory chains of
+ * gp_hmc_leapfrog do (same batch packing and modes: GP_HMC_PLAIN, GP_HMC_BATCHED, or
+ * GP_HMC_GRAPH, one persistent launch in which every chain's products share the GPU); each
+ * chain's weights and shifts are computed on the device for m = sigma^2_c and M = p->lambda_max
+ * or, when that is <= 0, the chain's Gershgorin bound max_i (A 1)_i (one extra product).
+ * p->precond_rank must be 0 (GP_ERR_UNSUPPORTED otherwise; gp_phi_refresh takes a Nystrom
+ * factor for one theta).  A pole is frozen once its residual is below p->tol |xi_c|; a chain
+ * ends when all of its poles are frozen, or after p->maxit iterations.  In the batched and graph
+ * modes nothing is synchronised; the plain mode reads each chain's state every few jobs.
+ *
+ *   X        device, packed per gp_batch, kernel precision (GP_NO_NOISE is rejected)
+ *   theta    device double, packed per chain as for gp_hmc_leapfrog; read only
+ *   xi       device, per chain as phi in gp_hmc_leapfrog, kernel precision
+ *   phi      device out, packed as xi; may be xi itself, must not overlap it otherwise
+ *   status   device int32 per chain: GP_PHI_* bits (0 = converged)
+ *   iters    device int32 per chain or NULL: multi-shift iterations used
+ *   bounds   device double[2] per chain or NULL: the m and M used
+ *   ws       gp_phi_chains_workspace_size bytes; the graph mode keys its captured launch by ws,
+ *            so a workspace shared with gp_hmc_leapfrog calls is recaptured at every switch
+ * Vectors are kept in the kernel precision (float for GP_F32 / GP_BF16X); scalars in double.
+ */
+gp_status gp_phi_refresh_chains(const gp_kernel *k, const gp_phi_params *p, int32_t mode,
+                                const gp_batch *b, const void *X, const double *theta,
+                                const void *xi, void *phi, int32_t *status, int32_t *iters,
+                                double *bounds, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Randomized Nystrom preconditioner (Section 3.1 after eq. pex, Section 3.2.3; rank 5 in

@@ -103,7 +103,29 @@ struct HmcChain {
   uint16_t *xh, *xl, *bimg;
   float *nrm;
   double cscale[kMaxD];  // per-dimension coordinate scale of the theta being solved at
+  // Gibbs refresh of phi (prog != kProgTrajectory): right-hand side xi and output phi (per chain,
+  // caller memory), bounds out [m, M] or null; in the workspace the shifted directions ps
+  // [np][n] and the per-pole state pst [np][kPst]; the unshifted CG scalars.
+  int prog;
+  const T *xi;
+  T *phio;
+  double *bounds_out;
+  T *ps;
+  double *pst;
+  double rr0, a_prev, b_prev, lmin, lmax;
 };
+
+// Chain programs: one trajectory (or random-walk update) of theta, or the Gibbs refresh of phi
+// (its Gershgorin bound, then its multi-shift iteration).
+enum HmcProg { kProgTrajectory = 0, kProgPhi = 1, kProgPhiBound = 2 };
+// Doubles of per-pole state of the refresh: weight, shift, zeta of the previous, current and next
+// iteration, the shifted step coefficient w_p alpha_p, the direction coefficients zp and bp, and
+// the active flag.
+namespace phs {
+enum { kW = 0, kLam, kZprev, kZ, kZnext, kCx, kZp, kBp, kAct };
+}
+constexpr int kPst = 9;
+constexpr int kPhiPoleMax = 64;  // most poles of the batched refresh
 
 // Waves per SIMD the persistent trajectory kernel is compiled for.  The default: in float the
 // tile variants up to d = 8 fit 128 VGPRs (4 waves) and those up to d = 16 fit 168 with a few
@@ -125,6 +147,13 @@ struct HmcRunParams {
   int cg_maxit;
   int max_jobs;  // (n_steps + 2) * (cg_maxit + 2) + 4: no trajectory can need more jobs
   int rwm;       // 1: random-walk Metropolis update theta' = theta + dt * pi, no kinetic energy
+  // Gibbs refresh (prog != kProgTrajectory): poles, per-pole tolerance, the caller's upper bound
+  // (<= 0: Gershgorin) and the relative widening of the Gershgorin bound for the product's rounding
+  int prog;
+  int n_poles;
+  double phi_tol;
+  double phi_lmax;
+  double phi_widen;
 };
 
 // Scheduling words of the batched launch, one per chain: (generation << 32) | claimed tiles.

@@ -35,6 +35,8 @@ hipError_t hmc_reset_f32(const HmcQueue &, hipStream_t);
 hipError_t hmc_reset_f64(const HmcQueue &, hipStream_t);
 hipError_t hmc_check_f32(void *, int, hipStream_t);
 hipError_t hmc_check_f64(void *, int, hipStream_t);
+hipError_t hmc_phi_poles_f32(void *, int, const HmcRunParams &, hipStream_t);
+hipError_t hmc_phi_poles_f64(void *, int, const HmcRunParams &, hipStream_t);
 
 namespace {
 
@@ -94,7 +96,8 @@ int plain_splits(int64_t n) {
   return (int)std::max<int64_t>(1, s);
 }
 
-size_t region_bytes(const InstInfo &in, int prec, int kind, int n_cs, int prank) {
+// Per-chain workspace; np > 0: a refresh of phi with np poles (shifted directions and pole state).
+size_t region_bytes(const InstInfo &in, int prec, int kind, int n_cs, int prank, int np) {
   const size_t es = prec == GP_F64 ? 8 : 4;
   const int64_t n = in.n;
   const int xm = xm_width(prec, in.d);
@@ -108,11 +111,12 @@ size_t region_bytes(const InstInfo &in, int prec, int kind, int n_cs, int prank)
   if (n_cs > 1) o += align256(sizeof(double) * n_cs * n);
   o += align256(sizeof(double) * (size_t)n_rb * n_cs * kHmcRec);
   if (prank > 0) o += align256(sizeof(double) * (size_t)(2 * n_rb + 2) * prank);  // pgp, pg, ph
+  if (np > 0) o += align256(es * (size_t)np * n) + align256(sizeof(double) * kPst * np);  // ps, pst
   return o;
 }
 
 ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec, int mode,
-                        int kind, int n_cheb, int prank) {
+                        int kind, int n_cheb, int prank, int np = 0) {
   ChainLayout L;
   const int nc = (int)inst.size() * chains;
   size_t o = 0;
@@ -134,7 +138,7 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
       L.per_chain.push_back(o);
       L.n_rb.push_back(n_rb);
       L.n_cs.push_back(n_cs);
-      o += region_bytes(in, prec, kind, n_cs, prank);
+      o += region_bytes(in, prec, kind, n_cs, prank, np);
     }
   }
   (void)n_cheb;
@@ -220,6 +224,19 @@ gp_status collect(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b,
   return GP_OK;
 }
 
+// Arguments of the refresh of phi (chain program kProgPhi); null for trajectories.
+struct PhiArgs {
+  const gp_phi_params *pp;
+  const void *xi;
+  void *phi;
+  double *bounds;
+};
+
+template <class P>
+P *at(P *base, int64_t off) {
+  return base ? base + off : nullptr;
+}
+
 template <typename T>
 void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int chains,
                  const ChainLayout &L,
@@ -227,7 +244,7 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
                  const void *X, const void *y, const void *phi, double *theta, double *pi,
                  void *x_warm, const double *u, double *H0, double *H1, int32_t *acc,
                  int32_t *status, int32_t *iters, int prec, const LaunchCfg &cfg,
-                 std::vector<HmcChain<T>> &out) {
+                 const PhiArgs *pa, std::vector<HmcChain<T>> &out) {
   out.assign(inst.size() * chains, HmcChain<T>());
   int64_t tofs = 0;
   int c = 0;
@@ -237,19 +254,25 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
       HmcChain<T> &ch = out[c];
       memset(&ch, 0, sizeof(ch));
       ch.X = (const T *)X + in.xoff;
-      ch.y = (const T *)y + in.off;
+      ch.y = at((const T *)y, in.off);
       const int64_t vo = (int64_t)chains * in.off + (int64_t)h * in.n;
-      ch.phi = (const T *)phi + vo;
-      ch.x = (T *)x_warm + vo;
+      ch.phi = at((const T *)phi, vo);
+      ch.x = at((T *)x_warm, vo);
       const int64_t to = (int64_t)chains * tofs + (int64_t)h * in.nth;
       ch.theta = theta + to;
-      ch.pi = pi + to;
-      ch.u = u ? u + c : nullptr;
-      ch.H0out = H0 + c;
-      ch.H1out = H1 + c;
-      ch.acc_out = acc + c;
+      ch.pi = at(pi, to);
+      ch.u = at(u, c);
+      ch.H0out = at(H0, c);
+      ch.H1out = at(H1, c);
+      ch.acc_out = at(acc, c);
       ch.status_out = status + c;
-      ch.iters_out = iters ? iters + c : nullptr;
+      ch.iters_out = at(iters, c);
+      if (pa) {
+        ch.prog = kProgPhi;
+        ch.xi = (const T *)pa->xi + vo;
+        ch.phio = (T *)pa->phi + vo;
+        ch.bounds_out = at(pa->bounds, 2 * (int64_t)c);
+      }
       for (int t = 0; t < in.nth; ++t) ch.minv[t] = p->inv_mass ? p->inv_mass[in.tofs + t] : 1.0;
       ch.prank = p->precond_rank;
       if (ch.prank > 0) {
@@ -308,6 +331,14 @@ void fill_chains(const std::vector<InstInfo> &inst, int kind, int n_cheb, int ch
         ch.pgp = (double *)r;
         ch.pg = ch.pgp + (size_t)2 * ch.n_rb * ch.prank;
         ch.ph = ch.pg + ch.prank;
+        r += align256(sizeof(double) * (size_t)(2 * ch.n_rb + 2) * ch.prank);
+      }
+      if (pa) {
+        const int np = pa->pp->n_poles;
+        ch.ps = (T *)r;
+        r += align256(es * (size_t)np * n);
+        ch.pst = (double *)r;
+        r += align256(sizeof(double) * kPst * np);
       }
     }
     tofs += in.nth;
@@ -366,15 +397,20 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
                             const void *X, const void *y, const void *phi, double *theta,
                             double *pi, void *x_warm, const double *u_accept, double *H0,
                             double *H1, int32_t *accepted, int32_t *status, int32_t *cg_iters,
-                            void *ws, size_t ws_bytes, hipStream_t stream, int rwm) {
+                            void *ws, size_t ws_bytes, hipStream_t stream, int rwm,
+                            const PhiArgs *pa = nullptr) {
   std::vector<InstInfo> inst;
   gp_status st = collect(k, p, b, inst);
   if (st) return st;
-  if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status)
+  if (pa) {
+    if (!X || !theta || !pa->xi || !pa->phi || !status)
+      return fail(GP_ERR_ARG, "X, theta, xi, phi and status must be non-NULL");
+  } else if (!X || !y || !phi || !theta || !pi || !x_warm || !H0 || !H1 || !accepted || !status) {
     return fail(GP_ERR_ARG, "X, y, phi, theta, pi, x_warm, H0, H1, accepted and status must be non-NULL");
+  }
   const int chains = b->chains_per_inst;
   const ChainLayout L = make_layout(inst, chains, k->prec, p->mode, k->kind, k->n_cheb,
-                                    p->precond_rank);
+                                    p->precond_rank, pa ? pa->pp->n_poles : 0);
   if (!ws || ws_bytes < L.total)
     return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
                 ws ? ws_bytes : (size_t)0);
@@ -398,12 +434,12 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   if (k->prec == GP_F64) {
     std::vector<HmcChain<double>> v;
     fill_chains<double>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                        accepted, status, cg_iters, k->prec, cfg, v);
+                        accepted, status, cg_iters, k->prec, cfg, pa, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   } else {
     std::vector<HmcChain<float>> v;
     fill_chains<float>(inst, k->kind, k->n_cheb, chains, L, w, p, X, y, phi, theta, pi, x_warm, u_accept, H0, H1,
-                       accepted, status, cg_iters, k->prec, cfg, v);
+                       accepted, status, cg_iters, k->prec, cfg, pa, v);
     desc.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
   }
   // chain order for the batched scheduler: largest problems first
@@ -448,6 +484,22 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 4) + 4,
                                         (int64_t)1 << 30);
   prm.rwm = rwm;
+  // the refresh of phi: without the caller's bound, a launch for the Gershgorin bound first
+  // (prm_b: the stage job and one product); then the poles; then the iteration (prm: the stage
+  // job and maxit products)
+  HmcRunParams prm_b;
+  const bool bound_launch = pa && !(pa->pp->lambda_max > 0.0);
+  if (pa) {
+    prm.prog = kProgPhi;
+    prm.n_poles = pa->pp->n_poles;
+    prm.phi_tol = pa->pp->tol;
+    prm.phi_lmax = pa->pp->lambda_max > 0.0 ? pa->pp->lambda_max : 0.0;
+    prm.phi_widen = k->prec == GP_F64 ? 1e-12 : (k->prec == GP_F32 ? 1e-5 : 1e-3);
+    prm.max_jobs = pa->pp->maxit + 4;
+    prm_b = prm;
+    prm_b.prog = kProgPhiBound;
+    prm_b.max_jobs = 4;
+  }
   HmcQueue qu;
   qu.word = (unsigned long long *)(w + L.hdr_word);
   qu.finished = (unsigned *)(w + L.hdr_fin);
@@ -464,43 +516,57 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   static_assert(offsetof(HmcChain<double>, done) - offsetof(HmcChain<double>, job) == kJobToDone * sizeof(int) &&
                     offsetof(HmcChain<float>, done) - offsetof(HmcChain<float>, job) == kJobToDone * sizeof(int),
                 "the plain-mode state read assumes job .. done are adjacent ints");
+  // Plain mode: chain c's kickoff, then its jobs one launch at a time until it is done.
+  auto plain_chain = [&](void *cp, int c, const HmcRunParams &pr) -> gp_status {
+    hipError_t e = f64 ? hmc_kickoff_f64(cp, 1, pr, qu, 0, stream) : hmc_kickoff_f32(cp, 1, pr, qu, 0, stream);
+    if (e != hipSuccess) return hip_fail(e, "kickoff");
+    const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
+    const int n_jobs = L.n_rb[c] * L.n_cs[c];
+    const int xm = xm_width(k->prec, inst[c / chains].d);
+    // chains are checked every kPlainCheck jobs: on a finished chain the tiles and the epilogue
+    // do nothing, so a few surplus launches are harmless
+    for (int64_t guard = 0;; ++guard) {
+      if (guard > (int64_t)pr.max_jobs + 2 + kPlainCheck)
+        return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
+      // job .. done are adjacent ints of the chain state: one read brings both
+      int state[kJobToDone + 1] = {};
+      if (guard % kPlainCheck == 0) {
+        e = hipMemcpyAsync(state, (char *)cp + off_job, sizeof(state), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
+        if (state[kJobToDone]) break;
+      }
+      const int dpc = inst[c / chains].dp;
+      e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, ch, pc, 0, stream)
+              : hmc_tiles_f32(cp, n_jobs, dpc, ch, pc, xm, stream);
+      // with column splits the product is gathered by a multi-workgroup pass before the
+      // (single-workgroup) epilogue
+      if (e == hipSuccess && L.n_cs[c] > 1)
+        e = f64 ? hmc_gather_f64(cp, L.n_rb[c], pc, stream)
+                : hmc_gather_f32(cp, L.n_rb[c], pc, stream);
+      if (e == hipSuccess)
+        e = f64 ? hmc_epilogue_f64(cp, pr, pc, stream) : hmc_epilogue_f32(cp, pr, pc, stream);
+      if (e != hipSuccess) return hip_fail(e, "plain-mode step");
+    }
+    return GP_OK;
+  };
+
   if (p->mode == GP_HMC_PLAIN) {
     for (int c = 0; c < nc; ++c) {
       void *cp = (char *)chains_dev + cb * c;
-      e = f64 ? hmc_kickoff_f64(cp, 1, prm, qu, 0, stream) : hmc_kickoff_f32(cp, 1, prm, qu, 0, stream);
-      if (e != hipSuccess) return hip_fail(e, "kickoff");
-      const size_t off_job = f64 ? offsetof(HmcChain<double>, job) : offsetof(HmcChain<float>, job);
-      const int n_jobs = L.n_rb[c] * L.n_cs[c];
-      const int xm = xm_width(k->prec, inst[c / chains].d);
-      // chains are checked every kPlainCheck jobs: on a finished chain the tiles and the epilogue
-      // do nothing, so a few surplus launches are harmless
-      for (int64_t guard = 0;; ++guard) {
-        if (guard > (int64_t)prm.max_jobs + 2 + kPlainCheck)
-          return fail(GP_ERR_HIP, "plain-mode chain %d did not finish", c);
-        // job .. done are adjacent ints of the chain state: one read brings both
-        int state[kJobToDone + 1] = {};
-        if (guard % kPlainCheck == 0) {
-          e = hipMemcpyAsync(state, (char *)cp + off_job, sizeof(state), hipMemcpyDeviceToHost, stream);
-          if (e == hipSuccess) e = hipStreamSynchronize(stream);
-          if (e != hipSuccess) return hip_fail(e, "plain-mode state read");
-          if (state[kJobToDone]) break;
+      if (pa) {
+        if (bound_launch) {
+          st = plain_chain(cp, c, prm_b);
+          if (st) return st;
         }
-        const int dpc = inst[c / chains].dp;
-        e = f64 ? hmc_tiles_f64(cp, n_jobs, dpc, ch, pc, 0, stream)
-                : hmc_tiles_f32(cp, n_jobs, dpc, ch, pc, xm, stream);
-        // with column splits the product is gathered by a multi-workgroup pass before the
-        // (single-workgroup) epilogue
-        if (e == hipSuccess && L.n_cs[c] > 1)
-          e = f64 ? hmc_gather_f64(cp, L.n_rb[c], pc, stream)
-                  : hmc_gather_f32(cp, L.n_rb[c], pc, stream);
-        if (e == hipSuccess)
-          e = f64 ? hmc_epilogue_f64(cp, prm, pc, stream) : hmc_epilogue_f32(cp, prm, pc, stream);
-        if (e != hipSuccess) return hip_fail(e, "plain-mode step");
+        e = f64 ? hmc_phi_poles_f64(cp, 1, prm, stream) : hmc_phi_poles_f32(cp, 1, prm, stream);
+        if (e != hipSuccess) return hip_fail(e, "pole weights");
       }
+      st = plain_chain(cp, c, prm);
+      if (st) return st;
     }
     return GP_OK;
   }
-
   // the defaults stand if a query fails
   int dev = 0, cus = 256, clk_khz = 100000;
   (void)hipGetDevice(&dev);
@@ -521,17 +587,31 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   // an idle workgroup gives up after 20 s without claimable work
   const long long idle_limit = (long long)clk_khz * 1000LL * 20LL;
 
-  auto enqueue = [&](hipStream_t s) -> hipError_t {
+  // one persistent launch of program pr: queue reset, every chain's kickoff, the scheduler, and
+  // the report of chains it did not finish
+  auto launch = [&](const HmcRunParams &pr, hipStream_t s) -> hipError_t {
     hipError_t r = f64 ? hmc_reset_f64(qu, s) : hmc_reset_f32(qu, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_kickoff_f64(chains_dev, nc, prm, qu, 1, s)
-            : hmc_kickoff_f32(chains_dev, nc, prm, qu, 1, s);
+    r = f64 ? hmc_kickoff_f64(chains_dev, nc, pr, qu, 1, s)
+            : hmc_kickoff_f32(chains_dev, nc, pr, qu, 1, s);
     if (r != hipSuccess) return r;
-    r = f64 ? hmc_persistent_f64(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, 0, waves, s)
-            : hmc_persistent_f32(chains_dev, nc, prm, qu, grid, idle_limit, dpmax, pc, ch, xmax,
+    r = f64 ? hmc_persistent_f64(chains_dev, nc, pr, qu, grid, idle_limit, dpmax, pc, ch, 0, waves, s)
+            : hmc_persistent_f32(chains_dev, nc, pr, qu, grid, idle_limit, dpmax, pc, ch, xmax,
                                  waves, s);
     if (r != hipSuccess) return r;
     return f64 ? hmc_check_f64(chains_dev, nc, s) : hmc_check_f32(chains_dev, nc, s);
+  };
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    if (pa) {
+      if (bound_launch) {
+        hipError_t r = launch(prm_b, s);
+        if (r != hipSuccess) return r;
+      }
+      hipError_t r = f64 ? hmc_phi_poles_f64(chains_dev, nc, prm, s)
+                         : hmc_phi_poles_f32(chains_dev, nc, prm, s);
+      if (r != hipSuccess) return r;
+    }
+    return launch(prm, s);
   };
 
   if (p->mode == GP_HMC_BATCHED) {
@@ -600,6 +680,74 @@ gp_status gp_rwm(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, 
   clear_error();
   return run_chains(k, p, b, X, y, phi, theta, xi, x_warm, u_accept, U0, U1, accepted, status,
                     cg_iters, ws, ws_bytes, stream, 1);
+}
+}  // extern "C"
+
+namespace gpk {
+namespace {
+
+// The refresh's own parameters, and the trajectory parameters that carry them through the
+// batch validation and the schedulers.
+gp_status phi_chain_params(const gp_kernel *k, const gp_phi_params *pp, int32_t mode,
+                           gp_hmc_params *hp) {
+  if (!k) return fail(GP_ERR_ARG, "kernel description is NULL");
+  if (!pp) return fail(GP_ERR_ARG, "phi parameters are NULL");
+  if (k->flags & GP_NO_NOISE) return fail(GP_ERR_ARG, "GP_NO_NOISE: A has no positive lower bound");
+  if (pp->n_poles < 1 || pp->n_poles > kPhiPoleMax)
+    return fail(GP_ERR_ARG, "n_poles = %d outside 1..%d", pp->n_poles, kPhiPoleMax);
+  if (!(pp->tol > 0.0)) return fail(GP_ERR_ARG, "tol must be > 0");
+  if (pp->maxit < 1) return fail(GP_ERR_ARG, "maxit must be >= 1");
+  if (!(pp->lambda_max <= 0.0 || std::isfinite(pp->lambda_max)))
+    return fail(GP_ERR_ARG, "lambda_max must be finite");
+  if (pp->precond_rank != 0)
+    return fail(GP_ERR_UNSUPPORTED,
+                "gp_phi_refresh_chains solves by multi-shift CG without a preconditioner "
+                "(precond_rank must be 0; gp_phi_refresh takes a Nystrom factor)");
+  memset(hp, 0, sizeof(*hp));
+  hp->cg_tol = pp->tol;
+  hp->cg_maxit = pp->maxit;
+  hp->mode = mode;
+  return GP_OK;
+}
+
+}  // namespace
+}  // namespace gpk
+
+extern "C" {
+
+size_t gp_phi_chains_workspace_size(const gp_kernel *k, const gp_phi_params *p, int32_t mode,
+                                    const gp_batch *b) {
+  gp_hmc_params hp;
+  std::vector<InstInfo> inst;
+  if (phi_chain_params(k, p, mode, &hp) != GP_OK || collect(k, &hp, b, inst) != GP_OK) return 0;
+  return make_layout(inst, b->chains_per_inst, k->prec, mode, k->kind, k->n_cheb, 0, p->n_poles)
+      .total;
+}
+
+gp_status gp_phi_refresh_chains(const gp_kernel *k, const gp_phi_params *p, int32_t mode,
+                                const gp_batch *b, const void *X, const double *theta,
+                                const void *xi, void *phi, int32_t *status, int32_t *iters,
+                                double *bounds, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  gp_hmc_params hp;
+  gp_status st = phi_chain_params(k, p, mode, &hp);
+  if (st) return st;
+  std::vector<InstInfo> inst;
+  st = collect(k, &hp, b, inst);
+  if (st) return st;
+  if (xi && phi && xi != phi) {
+    // xi and phi are packed alike: either the same array or disjoint
+    int64_t rows = 0;
+    for (const InstInfo &in : inst) rows = std::max(rows, in.off + in.n);
+    const size_t bytes = (size_t)rows * b->chains_per_inst * (k->prec == GP_F64 ? 8 : 4);
+    const char *a0 = (const char *)xi, *b0 = (const char *)phi;
+    if (a0 < b0 + bytes && b0 < a0 + bytes)
+      return fail(GP_ERR_ARG, "phi overlaps xi (only phi == xi is allowed)");
+  }
+  PhiArgs pa{p, xi, phi, bounds};
+  // the refresh reads theta and writes none of the trajectory outputs
+  return run_chains(k, &hp, b, X, nullptr, nullptr, const_cast<double *>(theta), nullptr, nullptr,
+                    nullptr, nullptr, nullptr, nullptr, status, iters, ws, ws_bytes, stream, 0, &pa);
 }
 }  // extern "C"
 

@@ -9,5 +9,6 @@
 #define GPK_HMC_CHAIN_BYTES hmc_chain_bytes_f32
 #define GPK_HMC_RESET hmc_reset_f32
 #define GPK_HMC_CHECK hmc_check_f32
+#define GPK_HMC_PHI_POLES hmc_phi_poles_f32
 #define GPK_XM 1
 #include "hmc_kernels.inc"

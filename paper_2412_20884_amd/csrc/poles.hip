@@ -2,15 +2,8 @@
 //     A^{-1/2} ~ sum_p w_p (A + lambda_p I)^{-1}                       (eq. pex)
 // with the weights and shifts of Appendix A (eq. msqdisc).
 //
-// Weights and shifts (host, double).  With m <= lambda_min(A), M >= lambda_max(A), k^2 = m / M
-// and K' = K(1 - k^2), the nodes t_j = i (j - 1/2) K' / N_p are purely imaginary; Jacobi's
-// imaginary transformation turns sn, cn, dn of modulus k at i u into sc, 1 / cn and dc of the
-// complementary parameter 1 - k^2 at u, so every shift and weight is real:
-//     lambda_j = m sc^2(u_j | 1 - k^2),   w_j = 2 K' sqrt(m) / (pi N_p) dn(u_j) / cn^2(u_j).
-// K' comes from the arithmetic-geometric mean, K(1 - k^2) = pi / (2 AGM(1, k)); sn, cn, dn from
-// the descending AGM (Landen) scale followed by the backward angle recursion; nodes past K'/2 are
-// evaluated at their reflection K' - u (also a node) so that cn never cancels.  The lower bound
-// is m = sigma^2 (every eigenvalue of A = sigma^2 I + K is at least the noise variance).
+// Weights and shifts (host, double): elliptic.h, with the lower bound m = sigma^2 (every
+// eigenvalue of A = sigma^2 I + K is at least the noise variance).
 //
 // Shifted solves.  All N_p systems (A + lambda_p I) x_p = xi share one Krylov space, so one
 // conjugate-gradient iteration on A drives all of them (multi-shift CG): the shifted residuals
@@ -30,6 +23,7 @@
 #include <vector>
 
 #include "common.h"
+#include "elliptic.h"
 #include "gpk.h"
 #include "vecops.h"
 
@@ -45,54 +39,6 @@ constexpr int kPoleMax = 64;     // most poles per call
 constexpr int kPhiMaxR = 32;     // most right-hand sides per call
 constexpr int kCheckEvery = 4;   // host convergence check period, iterations
 constexpr int kPcgBatch = 32;    // pole columns per preconditioned batch (gp_pcg_solve's limit)
-
-// ---- Jacobi elliptic functions by the AGM (host) ---------------------------------------------
-
-// K(1 - k^2) for 0 < k <= 1 from the arithmetic-geometric mean of 1 and k.
-double ellk_complement(double k) {
-  double a = 1.0, b = k;
-  for (int it = 0; it < 64 && fabs(a - b) > 1e-16 * a; ++it) {
-    const double an = 0.5 * (a + b);
-    b = sqrt(a * b);
-    a = an;
-  }
-  return M_PI / (2.0 * a);
-}
-
-// sn, cn, dn(u | mpar) for parameter mpar = 1 - k^2 in [0, 1), given k = sqrt(1 - mpar): the
-// descending AGM scale a_n, c_n from (1, k, sqrt(mpar)), then phi_N = 2^N a_N u and
-// phi_{n-1} = (phi_n + asin(c_n sin(phi_n) / a_n)) / 2;  sn = sin(phi_0), cn = cos(phi_0),
-// dn = cos(phi_0) / cos(phi_1 - phi_0).
-void jacobi_sncndn(double u, double k, double *sn, double *cn, double *dn) {
-  const double cpar = sqrt((1.0 - k) * (1.0 + k));  // sqrt(mpar)
-  if (cpar < 1e-300) {  // mpar = 0: circular functions
-    *sn = sin(u);
-    *cn = cos(u);
-    *dn = 1.0;
-    return;
-  }
-  double a[64], c[64];
-  a[0] = 1.0;
-  c[0] = cpar;
-  double b = k;
-  int n = 0;
-  while (fabs(c[n]) > 1e-17 * a[n] && n < 62) {
-    const double an = 0.5 * (a[n] + b);
-    c[n + 1] = 0.5 * (a[n] - b);
-    b = sqrt(a[n] * b);
-    a[n + 1] = an;
-    ++n;
-  }
-  double phi = ldexp(a[n] * u, n);
-  double phi_next = phi;  // phi_1 once the recursion ends
-  for (int j = n; j >= 1; --j) {
-    phi_next = phi;
-    phi = 0.5 * (phi + asin(c[j] * sin(phi) / a[j]));
-  }
-  *sn = sin(phi);
-  *cn = cos(phi);
-  *dn = n >= 1 ? cos(phi) / cos(phi_next - phi) : 1.0;
-}
 
 // ---- device kernels ---------------------------------------------------------------------------
 
@@ -663,22 +609,9 @@ gp_status gp_pole_weights(double m, double M, int32_t n_poles, double *w, double
     return fail(GP_ERR_ARG, "need 0 < m <= M < inf (m = %g, M = %g)", m, M);
   const double k = sqrt(m / M);
   const double kp = ellk_complement(k);
-  const double scale = 2.0 * kp * sqrt(m) / (M_PI * n_poles);
-  for (int j = 0; j < n_poles; ++j) {
-    double sn, cn, dn;
-    if (2 * j + 1 <= n_poles) {  // u_j <= K'/2: direct
-      jacobi_sncndn((j + 0.5) * kp / n_poles, k, &sn, &cn, &dn);
-      shift[j] = m * (sn / cn) * (sn / cn);
-      w[j] = scale * dn / (cn * cn);
-    } else {
-      // u_j > K'/2, where cn(u_j) -> 0 would lose relative accuracy: reflect to v = K' - u_j
-      // (itself a node), sn(u) = cd(v), cn(u) = k sd(v), dn(u) = k nd(v), so that
-      // m sc^2(u) = M cn^2(v) / sn^2(v) and dn(u) / cn^2(u) = dn(v) / (k sn^2(v))
-      jacobi_sncndn((n_poles - j - 0.5) * kp / n_poles, k, &sn, &cn, &dn);
-      shift[j] = M * (cn / sn) * (cn / sn);
-      w[j] = scale * dn / (k * sn * sn);
-    }
-  }
+  double sa[kAgmMax], sc[kAgmMax];
+  const int ns = agm_scale(k, sa, sc);
+  for (int j = 0; j < n_poles; ++j) pole_node(m, M, n_poles, j, k, kp, sa, sc, ns, w + j, shift + j);
   return GP_OK;
 }
 

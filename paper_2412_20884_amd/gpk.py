@@ -19,7 +19,7 @@ F64, F32, BF16X = 0, 1, 2
 NO_NOISE = 1
 PLAIN, BATCHED, GRAPH = 0, 1, 2
 CHAIN_CG_MAXIT, CHAIN_NONFINITE_H, CHAIN_NONFINITE_THETA, CHAIN_ABORTED, CHAIN_FP_MAXIT = 1, 2, 4, 8, 16
-PHI_CG_MAXIT, PHI_NONFINITE = 1, 2
+PHI_CG_MAXIT, PHI_NONFINITE, PHI_ABORTED = 1, 2, 4
 CG_MAXIT, CG_NONFINITE = 1, 2
 
 EXPORTED = (
@@ -29,6 +29,7 @@ EXPORTED = (
     "gp_pole_weights", "gp_phi_workspace_size", "gp_phi_refresh", "gp_nystrom_workspace_size",
     "gp_nystrom", "gp_pcg_workspace_size", "gp_pcg_solve", "gp_implicit_workspace_size",
     "gp_hmc_implicit", "gp_rwm", "gp_kmatvec_noalloc", "gp_tune_hmc_workspace_size", "gp_tune_hmc",
+    "gp_phi_chains_workspace_size", "gp_phi_refresh_chains",
 )
 
 
@@ -138,6 +139,13 @@ def lib():
     L.gp_phi_refresh.restype = _i32
     L.gp_phi_refresh.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams), _i64, _vp, _vp,
                                  _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gp_phi_chains_workspace_size.restype = _sz
+    L.gp_phi_chains_workspace_size.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams),
+                                               _i32, ctypes.POINTER(Batch)]
+    L.gp_phi_refresh_chains.restype = _i32
+    L.gp_phi_refresh_chains.argtypes = [ctypes.POINTER(Kernel), ctypes.POINTER(PhiParams), _i32,
+                                        ctypes.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        _vp, _sz, _vp]
     L.gp_nystrom_workspace_size.restype = _sz
     L.gp_nystrom_workspace_size.argtypes = [ctypes.POINTER(Kernel), _i64, _i32]
     L.gp_nystrom.restype = _i32
@@ -591,6 +599,69 @@ def pole_weights(m, M, n_poles=15):
 
 def phi_workspace_size(kernel, params, n, r):
     return int(lib().gp_phi_workspace_size(ctypes.byref(kernel), ctypes.byref(params), int(n), int(r)))
+
+
+_PHI_WS = {}
+
+
+def phi_refresh_chains(X, theta, xi, kind, n_points, offsets, chains, d=None, x_offsets=None,
+                       prec=None, n_poles=15, tol=1e-8, maxit=2000, lambda_max=None, mode=BATCHED,
+                       out=None, ws=None, n_cheb=0, outputs=None):
+    """phi_c = A(theta_c)^{-1/2} xi_c for every chain of a batch through gp_phi_refresh_chains
+    (packing of gp_hmc_leapfrog: xi and phi as its phi, theta as its theta).  out: the phi tensor
+    to write (may be xi itself; default a new one).  outputs: the dict an earlier call returned, to
+    be written again (graph mode then replays its captured launches).
+
+    Returns dict(phi, status, iters, bounds) with bounds one (m, M) row per chain."""
+    dev = X.device
+    dt_ = X.dtype
+    _same(dev, dt_, xi=xi, out=out)
+    _same(dev, torch.float64, theta=theta)
+    for name, t in (("X", X), ("theta", theta), ("xi", xi), ("out", out)):
+        if t is not None and not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    n_inst = len(n_points)
+    dims = [X.shape[1]] * n_inst if d is None else list(d)
+    _check_batch(X, None, xi, theta, None, out, None, kind, n_points, offsets, chains, dims,
+                 x_offsets, n_cheb)
+    k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
+    prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0), 0, None, None)
+    npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])
+    offs = (ctypes.c_int64 * n_inst)(*[int(v) for v in offsets])
+    dd = (ctypes.c_int32 * n_inst)(*[int(v) for v in dims]) if d is not None else None
+    xo = (ctypes.c_int64 * n_inst)(*[int(v) for v in x_offsets]) if x_offsets is not None else None
+    b = Batch(n_inst, int(chains), npts, offs, dd, xo)
+    nc = n_inst * int(chains)
+    if outputs is not None:
+        st, it, bnd = outputs["status"], outputs["iters"], outputs["bounds"]
+        for name, t, dt, m in (("status", st, torch.int32, nc), ("iters", it, torch.int32, nc),
+                               ("bounds", bnd, torch.float64, 2 * nc)):
+            if t.dtype != dt or t.numel() != m or t.device != dev or not t.is_contiguous():
+                raise ValueError(f"outputs[{name!r}] must be a contiguous {dt} tensor of {m} on {dev}")
+        if out is None:
+            out = outputs["phi"]
+    else:
+        st = torch.zeros(nc, dtype=torch.int32, device=dev)
+        it = torch.zeros(nc, dtype=torch.int32, device=dev)
+        bnd = torch.zeros((nc, 2), dtype=torch.float64, device=dev)
+    if out is None:
+        out = torch.empty_like(xi)
+    nbytes = int(lib().gp_phi_chains_workspace_size(ctypes.byref(k), ctypes.byref(prm), int(mode),
+                                                    ctypes.byref(b)))
+    if nbytes == 0:
+        _check(lib().gp_phi_refresh_chains(ctypes.byref(k), ctypes.byref(prm), int(mode),
+                                           ctypes.byref(b), None, None, None, None, None, None,
+                                           None, None, 0, None))
+    if ws is None:
+        key = (str(dev), nbytes)
+        ws = _PHI_WS.get(key)
+        if ws is None:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            _PHI_WS[key] = ws
+    _check(lib().gp_phi_refresh_chains(ctypes.byref(k), ctypes.byref(prm), int(mode), ctypes.byref(b),
+                                       _p(X), _p(theta), _p(xi), _p(out), _p(st), _p(it), _p(bnd),
+                                       _p(ws), ws.numel(), _stream(dev)))
+    return {"phi": out, "status": st, "iters": it, "bounds": bnd}
 
 
 def phi_refresh(X, theta, xi, kind="iso", prec=None, n_poles=15, tol=1e-8, maxit=2000,

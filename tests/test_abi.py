@@ -163,6 +163,50 @@ def test_trajectory_tune_entries_and_validation(tmp_path):
     assert L.gp_tune_hmc(ctypes.byref(k), ctypes.byref(prm), ctypes.byref(bad), None, 0, None) == 2
 
 
+def test_phi_chains_validation():
+    """gp_phi_refresh_chains checks its parameters, the batch and the workspace before any HIP
+    call; its workspace holds the trajectory workspace's vectors plus the shifted directions."""
+    L = gpk.lib()
+    vp = ctypes.c_void_p
+    k = gpk.Kernel(gpk.ARD, gpk.F32, 4, 0, 0)
+    npts = (ctypes.c_int64 * 2)(1000, 500)
+    offs = (ctypes.c_int64 * 2)(0, 1000)
+    dd = (ctypes.c_int32 * 2)(4, 16)
+    b = gpk.Batch(2, 3, npts, offs, dd, None)
+    hp = gpk.HmcParams(0, 0.0, 1e-6, 100, gpk.BATCHED, None, 0, None, None, None)
+
+    def ws_size(pp, mode=gpk.BATCHED, kk=k, bb=b):
+        return L.gp_phi_chains_workspace_size(ctypes.byref(kk), ctypes.byref(pp), mode, ctypes.byref(bb))
+
+    def call(pp, kk=k, xi=1 << 12, phi=1 << 40, ws=None, wsb=0, mode=gpk.BATCHED):
+        return L.gp_phi_refresh_chains(ctypes.byref(kk), ctypes.byref(pp), mode, ctypes.byref(b),
+                                       vp(1 << 30), vp(1 << 31), vp(xi), vp(phi), vp(1 << 32), None,
+                                       None, vp(ws) if ws else None, wsb, None)
+
+    ok = gpk.PhiParams(15, 1e-6, 100, 0.0, 0, None, None)
+    n15 = ws_size(ok)
+    traj = L.gp_hmc_workspace_size(ctypes.byref(k), ctypes.byref(hp), ctypes.byref(b))
+    # 6 chains of 1000 / 500 float rows, 15 directions each
+    assert n15 >= traj + 4 * 15 * 3 * (1000 + 500)
+    assert ws_size(gpk.PhiParams(30, 1e-6, 100, 0.0, 0, None, None)) > n15
+    assert ws_size(ok, mode=gpk.PLAIN) > 0 and ws_size(ok, mode=7) == 0
+    for bad in (gpk.PhiParams(0, 1e-6, 100, 0.0, 0, None, None),
+                gpk.PhiParams(65, 1e-6, 100, 0.0, 0, None, None),
+                gpk.PhiParams(15, 0.0, 100, 0.0, 0, None, None),
+                gpk.PhiParams(15, 1e-6, 0, 0.0, 0, None, None),
+                gpk.PhiParams(15, 1e-6, 100, float("nan"), 0, None, None)):
+        assert ws_size(bad) == 0
+        assert call(bad) == 1
+    assert call(gpk.PhiParams(15, 1e-6, 100, 0.0, 5, vp(8), vp(8))) == 3
+    assert call(ok, kk=gpk.Kernel(gpk.ARD, gpk.F32, 4, gpk.NO_NOISE, 0)) == 1
+    assert call(ok, kk=gpk.Kernel(gpk.CHEB, gpk.BF16X, 2, 0, 2)) == 3
+    assert call(ok) == 4                                   # no workspace
+    assert call(ok, ws=1 << 20, wsb=n15 - 1) == 4          # one byte short
+    assert call(ok, xi=1 << 12, phi=(1 << 12) + 8) == 1    # phi overlaps xi
+    bad_b = gpk.Batch(2, 0, npts, offs, dd, None)
+    assert ws_size(ok, bb=bad_b) == 0
+
+
 def test_cheb_workspace_and_tuner():
     L = gpk.lib()
     k = ctypes.byref(gpk.Kernel(gpk.CHEB, gpk.F32, 2, 0, 3))
