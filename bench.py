@@ -271,6 +271,26 @@ def bench_leapfrog(modes=("graph", "graph_nystrom", "plain"), subset=8, group=0,
                "multishift_cg_iterations": it_phi, "n_poles": 15, "tol": 1e-6,
                "workload": "phi = A(theta_0)^{-1/2} xi for the 8 chains of each instance of the subset "
                            "below (one call per instance, 8 right-hand sides), FP32"}
+    # the same refresh for every chain of every instance in one launch of the batched refresh,
+    # each chain as its own system (the form the sampler needs once chains' theta differ)
+    xi_all = torch.tensor(np.concatenate([b["xi"].ravel() for b in inst]), dtype=torch.float32, device=dev)
+    th_all = torch.tensor(np.concatenate([np.tile(b["theta"], C) for b in inst]), dtype=torch.float64,
+                          device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = gpk.phi_refresh_chains(X, th_all, xi_all, "ard", ns, offs, C, d=ds, x_offsets=xoffs, tol=1e-6,
+                                maxit=3000, mode=gpk.BATCHED)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    if np.any(rb["status"].cpu().numpy() != 0):
+        raise RuntimeError("batched phi refresh did not converge")
+    dphi = (rb["phi"] - phi).norm().item() / phi.norm().item()
+    refresh["one_launch_all_chains"] = {
+        "chains_refreshed_per_s": cols / t_b, "seconds": t_b,
+        "max_multishift_iterations": int(rb["iters"].max()),
+        "rel_diff_vs_per_instance_calls": dphi,
+        "note": "gp_phi_refresh_chains, BATCHED mode: every chain's product is its own R = 1 job "
+                "(the per-instance calls share one R = 8 product between an instance's chains)"}
     log(f"phi refresh: {refresh}")
     th0 = np.concatenate([np.tile(b["theta"], C) for b in inst])
     pi0 = np.concatenate([b["pi"].ravel() for b in inst])
@@ -743,10 +763,11 @@ def bench_cheb2d(tol=1e-6, rank=500, refresh_every=5):
         th = torch.tensor(np.tile(wl["theta"], C), dtype=torch.float64, device=dev)
         x = torch.zeros(n * C, dtype=torch.float64, device=dev)
         phi = torch.empty(n * C, dtype=torch.float64, device=dev)
+        xib = torch.empty(n * C, dtype=torch.float64, device=dev)
         pi = torch.empty(C * nt, dtype=torch.float64, device=dev)
         u = torch.empty(C, dtype=torch.float64, device=dev)
         acc, cg, ph_it, dH, t_phi, t_nys = 0, 0, 0, [], 0.0, 0.0
-        pre, res = None, None
+        pre, res, ph_out = None, None, None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(nu):
@@ -757,13 +778,25 @@ def bench_cheb2d(tol=1e-6, rank=500, refresh_every=5):
                 torch.cuda.synchronize()
                 t_nys += time.perf_counter() - t1
             t1 = time.perf_counter()
-            for c in range(C):
-                r = gpk.phi_refresh(X, th[c * nt:(c + 1) * nt], xi[k, c], "cheb", tol=tol, maxit=3000,
-                                    n_cheb=nc, precond=pre)
-                phi[c * n:(c + 1) * n] = r["phi"].reshape(-1)
-                ph_it += int(r["iters"][0])
-                if int(r["status"][0]) != 0:
-                    raise RuntimeError(f"cheb2d: phi refresh of chain {c} failed at update {k}")
+            if use_precond:
+                # the paper's form: the shifted systems of each chain by preconditioned CG
+                for c in range(C):
+                    r = gpk.phi_refresh(X, th[c * nt:(c + 1) * nt], xi[k, c], "cheb", tol=tol,
+                                        maxit=3000, n_cheb=nc, precond=pre)
+                    phi[c * n:(c + 1) * n] = r["phi"].reshape(-1)
+                    ph_it += int(r["iters"][0])
+                    if int(r["status"][0]) != 0:
+                        raise RuntimeError(f"cheb2d: phi refresh of chain {c} failed at update {k}")
+            else:
+                # every chain at its own theta in one graph-replayed launch (multi-shift CG)
+                xib.copy_(xi[k].reshape(-1))
+                ph_out = gpk.phi_refresh_chains(X.view(-1, 1), th, xib, "cheb", [n], [0], C, d=[2],
+                                                tol=tol, maxit=3000, n_cheb=nc, mode=gpk.GRAPH,
+                                                out=phi, outputs=ph_out)
+                st = ph_out["status"].cpu().numpy()
+                if np.any(st != 0):
+                    raise RuntimeError(f"cheb2d: batched phi refresh status {st.tolist()} at update {k}")
+                ph_it += int(ph_out["iters"].sum())
             torch.cuda.synchronize()
             t_phi += time.perf_counter() - t1
             pi.copy_(torch.from_numpy(wl["pi"][k].ravel()))
@@ -787,13 +820,41 @@ def bench_cheb2d(tol=1e-6, rank=500, refresh_every=5):
                 "mean_phi_iters": ph_it / (nu * C), "max_abs_dH": float(np.max(np.abs(dH))),
                 "theta_final": th.cpu().numpy()}
 
+    # the refresh alone at the chains' start theta: per-chain calls against one batched launch
+    th0 = torch.tensor(np.tile(wl["theta"], C), dtype=torch.float64, device=dev)
+    xi0 = xi[0].reshape(-1).contiguous()
+    phi_a = torch.empty(n * C, dtype=torch.float64, device=dev)
+    gpk.phi_refresh_chains(X.view(-1, 1), th0, xi0, "cheb", [n], [0], C, d=[2], tol=tol, maxit=3000,
+                           n_cheb=nc, mode=gpk.BATCHED)  # warm-up (workspace, first launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(C):
+        r = gpk.phi_refresh(X, th0[c * nt:(c + 1) * nt], xi[0, c], "cheb", tol=tol, maxit=3000, n_cheb=nc)
+        phi_a[c * n:(c + 1) * n] = r["phi"].reshape(-1)
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rb = gpk.phi_refresh_chains(X.view(-1, 1), th0, xi0, "cheb", [n], [0], C, d=[2], tol=tol,
+                                maxit=3000, n_cheb=nc, mode=gpk.BATCHED)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    refresh_cmp = {"per_chain_calls_seconds": t_per, "one_launch_seconds": t_one,
+                   "speedup": t_per / t_one,
+                   "rel_diff": (rb["phi"] - phi_a).norm().item() / phi_a.norm().item(),
+                   "iterations": rb["iters"].cpu().numpy().tolist(),
+                   "note": f"{C} chains at the start theta, FP64, multi-shift CG to tol {tol:g}: "
+                           "gp_phi_refresh per chain against one gp_phi_refresh_chains launch"}
+    log(f"cheb2d refresh: {refresh_cmp}")
     plain = run(False)
     prec = run(True)
     dtheta = float(np.max(np.abs(plain.pop("theta_final") - prec.pop("theta_final"))))
     out = {"workload": f"cheb2d: N={n}, d=2 (half uniform on [-1,1]^2, half in 8 clusters), "
                        f"Chebyshev-amplitude SE, N_cheb={nc} ({nt} hyperparameters), FP64, {C} chains, "
                        f"{nu} updates of {wl['n_steps']} leapfrog steps of dt {wl['dt']:g}, CG tol {tol:g}, "
-                       "phi refreshed per chain and update on the device, trajectories in graph mode",
+                       "phi refreshed for every chain at every update on the device (plain CG run: all "
+                       "chains in one graph-replayed gp_phi_refresh_chains launch; preconditioned run: "
+                       "per chain, preconditioned CG per pole), trajectories in graph mode",
+           "phi_refresh_per_chain_vs_one_launch": refresh_cmp,
            "graph_plain_cg": plain,
            f"graph_nystrom_rank{rank}_every{refresh_every}": prec,
            "max_abs_theta_diff_between_the_two": dtheta}
