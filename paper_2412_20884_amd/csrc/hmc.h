@@ -154,6 +154,9 @@ struct HmcRunParams {
   double phi_tol;
   double phi_lmax;
   double phi_widen;
+  // 1: the chain's epilogue forms q from the column-split partials (persistent launches); 0: the
+  // plain mode's gather kernel has formed it
+  int epi_gather;
 };
 
 // Scheduling words of the batched launch, one per chain: (generation << 32) | claimed tiles.

@@ -96,6 +96,26 @@ int plain_splits(int64_t n) {
   return (int)std::max<int64_t>(1, s);
 }
 
+// Persistent launches: a batch with fewer row-block jobs than kSplitTarget splits every product
+// and force-pass job's columns (at most kMaxSplits ways, at least kMinSplitCols columns each)
+// until it has about that many, so a few chains still fill the GPU (one FP64 row-block job of a
+// 3000-point chain is ~150 us of one workgroup).  Not for GP_BF16X chains (their jobs take no
+// splits) or preconditioned launches (their row-block partials of U^T w come from the complete
+// q).  The split partials are summed in the chain's epilogue.
+constexpr int64_t kSplitTarget = 2048;
+constexpr int kMaxSplits = 16;
+constexpr int64_t kMinSplitCols = 256;
+
+int persistent_splits(const std::vector<InstInfo> &inst, int chains, int prec, int prank) {
+  if (prank > 0) return 1;
+  int64_t jobs = 0;
+  for (const InstInfo &in : inst) {
+    if (xm_width(prec, in.d)) return 1;
+    jobs += row_blocks(in.n, 0) * chains;
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplits, kSplitTarget / std::max<int64_t>(1, jobs)));
+}
+
 // Per-chain workspace; np > 0: a refresh of phi with np poles (shifted directions and pole state).
 size_t region_bytes(const InstInfo &in, int prec, int kind, int n_cs, int prank, int np) {
   const size_t es = prec == GP_F64 ? 8 : 4;
@@ -130,9 +150,11 @@ ChainLayout make_layout(const std::vector<InstInfo> &inst, int chains, int prec,
   o = align256(o + 4 * (size_t)nc);
   L.chains = o;
   o = align256(o + chain_bytes(prec) * (size_t)nc);
+  const int ps = persistent_splits(inst, chains, prec, prank);
   for (const InstInfo &in : inst) {
     const int xm = xm_width(prec, in.d);
-    const int n_cs = (mode == GP_HMC_PLAIN && !xm) ? plain_splits(in.n) : 1;
+    int n_cs = 1;
+    if (!xm) n_cs = mode == GP_HMC_PLAIN ? plain_splits(in.n) : std::min<int64_t>(ps, std::max<int64_t>(1, in.n / kMinSplitCols));
     const int n_rb = (int)row_blocks(in.n, xm);
     for (int h = 0; h < chains; ++h) {
       L.per_chain.push_back(o);
@@ -484,6 +506,7 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 4) + 4,
                                         (int64_t)1 << 30);
   prm.rwm = rwm;
+  prm.epi_gather = p->mode != GP_HMC_PLAIN;
   // the refresh of phi: without the caller's bound, a launch for the Gershgorin bound first
   // (prm_b: the stage job and one product); then the poles; then the iteration (prm: the stage
   // job and maxit products)
