@@ -101,9 +101,12 @@ int plain_splits(int64_t n) {
 // until it has about that many, so a few chains still fill the GPU (one FP64 row-block job of a
 // 3000-point chain is ~150 us of one workgroup).  Not for GP_BF16X chains (their jobs take no
 // splits) or preconditioned launches (their row-block partials of U^T w come from the complete
-// q).  The split partials are summed in the chain's epilogue.
+// q).  The split partials are summed in the chain's epilogue, whose latency grows with the
+// split count: on 10 FP64 chains of 3000 points a multi-shift iteration took 429 / 263 / 204 /
+// 287 / 333 / 370 us with at most 1 / 2 / 4 / 6 / 8 / 16 splits, a CG iteration 379 / 209 / 224 /
+// 230 / 259 / 312 us.
 constexpr int64_t kSplitTarget = 2048;
-constexpr int kMaxSplits = 16;
+constexpr int kMaxSplits = 4;
 constexpr int64_t kMinSplitCols = 256;
 
 int persistent_splits(const std::vector<InstInfo> &inst, int chains, int prec, int prank) {
