@@ -104,8 +104,10 @@ int plain_splits(int64_t n) {
 // q).  The split partials are summed in the chain's epilogue, whose latency grows with the
 // split count: on 10 FP64 chains of 3000 points a multi-shift iteration took 429 / 263 / 204 /
 // 287 / 333 / 370 us with at most 1 / 2 / 4 / 6 / 8 / 16 splits, a CG iteration 379 / 209 / 224 /
-// 230 / 259 / 312 us.
-constexpr int64_t kSplitTarget = 2048;
+// 230 / 259 / 312 us.  The target: 32 float chains of 6k-19k points (about 1,500 row blocks) ran
+// 20-step trajectories at 107.7 / 137.6 / 130.7 / 126.1 chain-steps/s with 1 / 2 / 3 / 4 splits
+// (the splits shorten the end of the launch, when only the largest chains still have jobs).
+constexpr int64_t kSplitTarget = 4096;
 constexpr int kMaxSplits = 4;
 constexpr int64_t kMinSplitCols = 256;
 
