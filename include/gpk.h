@@ -312,9 +312,10 @@ gp_status gp_rwm(const gp_kernel *k, const gp_hmc_params *p, const gp_batch *b, 
  * precision, kernel kind, largest padded d, kernel variant (preconditioned, Chebyshev-amplitude,
  * GP_BF16X), floor(log2) of its number of chains and of its largest N -- gp_tune_hmc times launch
  * configurations on synthetic inputs of the batch's geometry (the instances' N and d and the
- * chains per instance of `b`; a 1-step trajectory with 4 CG iterations per solve, so every
- * configuration runs the same jobs), one knob at a time from the defaults, and records the
- * fastest in the tuning table of gp_tune_products, which later gp_hmc_leapfrog / gp_rwm calls of
+ * chains per instance of `b`; a 1-step trajectory with 8 CG iterations per solve, so every
+ * configuration runs the same jobs), one knob at a time from the defaults (a candidate must be
+ * more than 4% faster to replace the current choice), and records the winner in the tuning
+ * table of gp_tune_products, which later gp_hmc_leapfrog / gp_rwm calls of
  * that class use.  Knobs: the persistent kernel compiled for its default or its alternative
  * number of waves per SIMD, and the product jobs' columns per trip (4 or 2 for padded d <= 8,
  * 2 or 1 above).  No configuration changes any result: the sums run in the same order.  `p` supplies the preconditioner rank
