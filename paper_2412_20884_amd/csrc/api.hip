@@ -27,20 +27,49 @@ gp_status hip_fail(hipError_t e, const char *where) {
   return fail(GP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-// Final fixed-order sum of the per-block records.  One thread per record entry; quad receives
-// the first nq column sums.
-__global__ void reduce_records(const double *rp, int64_t np, const double *rf, int64_t nf,
-                               int nrec, int nth, int L, double *grad, double *quad, int nq) {
-  const int e = threadIdx.x;
-  if (e >= nrec) return;
+// Final fixed-order sum of the per-block records; grad receives the theta entries, quad the
+// first nq column sums.
+__global__ __launch_bounds__(256) void reduce_records(const double *rp, int64_t np,
+                                                      const double *rf, int64_t nf, int nrec,
+                                                      int nth, int L, double *grad, double *quad,
+                                                      int nq) {
+  // G (a power of two) groups of nrec threads: group g sums the records g, g + G, ... of the
+  // pair blocks, then of the final blocks, with 8 loads in flight; then a pairwise tree over
+  // the groups.  The order depends on nrec and the record counts only: deterministic.
+  __shared__ double part[256];
+  int G = 1;
+  while (2 * G * nrec <= 256) G *= 2;
+  const int t = threadIdx.x, g = t / nrec, e = t - g * nrec;
   double s = 0.0;
-  for (int64_t b = 0; b < np; ++b) s += rp[b * nrec + e];
-  for (int64_t b = 0; b < nf; ++b) s += rf[b * nrec + e];
-  if (e < nth) {
-    const double f = (e >= 1 && e <= L) ? 2.0 * kLn2 : 1.0;
-    if (grad) grad[e] = s * f;
-  } else if (quad && e - nth < nq) {
-    quad[e - nth] = s;
+  if (g < G) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const double *r = pass ? rf : rp;
+      const int64_t m = pass ? nf : np;
+      for (int64_t b0 = g; b0 < m; b0 += 8 * (int64_t)G) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t b = b0 + (int64_t)u * G;
+          v[u] = b < m ? r[b * nrec + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+    }
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int h = G / 2; h > 0; h /= 2) {
+    if (g < h) part[t] += part[t + h * nrec];
+    __syncthreads();
+  }
+  if (t >= nrec) return;
+  s = part[t];
+  if (t < nth) {
+    const double f = (t >= 1 && t <= L) ? 2.0 * kLn2 : 1.0;
+    if (grad) grad[t] = s * f;
+  } else if (quad && t - nth < nq) {
+    quad[t - nth] = s;
   }
 }
 
@@ -105,7 +134,7 @@ hipError_t launch_pass(const PassDesc &p, hipStream_t s) {
 
 hipError_t launch_reduce(const PassDesc &p, double *grad, double *quad, hipStream_t s, int nq) {
   if (!grad && !quad) return hipSuccess;
-  reduce_records<<<1, 128, 0, s>>>(p.rec_pair, pair_blocks(p), p.rec_fin, fin_blocks(p),
+  reduce_records<<<1, 256, 0, s>>>(p.rec_pair, pair_blocks(p), p.rec_fin, fin_blocks(p),
                                    p.nrec, p.nth, p.kind == 0 ? 1 : p.d, grad, quad,
                                    nq < 0 ? p.nrec - p.nth : nq);
   return hipGetLastError();

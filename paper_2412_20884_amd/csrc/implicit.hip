@@ -10,8 +10,12 @@
 // stacked into one vector v = (theta, pi, x); Anderson acceleration with history k keeps the
 // last k pairs (f_i = Phi(v_i) - v_i, g_i = Phi(v_i)) and sets v = sum_i alpha_i g_i with
 // alpha minimising |sum_i alpha_i f_i| subject to sum_i alpha_i = 1 (k = 0: plain Picard
-// iteration).  The (theta, pi) parts live on the host in double, the x parts on the device; the
-// inner products and the combination run in the kernels below.  c comes from power iterations
+// iteration).  Everything of an iteration runs on the device: the (theta, pi) parts and the
+// history's Gram matrix in double in a small state block, the convergence test, the
+// least-squares weights and the combination in one single-workgroup kernel (imp_update), the x
+// parts in the streaming kernels below.  The host enqueues iterations without waiting and reads
+// the state's convergence flag every kCheck iterations (iterations enqueued after convergence
+// change nothing).  c comes from power iterations
 // on A(theta_0) (ten in the paper); with a Nystrom factor R = P^{-1} / c, P the preconditioner of
 // A(theta_0) and c ~ rho(P^{-1} A(theta_0)).  The trajectory ends with a solve at theta_1 for the energy,
 // as for the leapfrog integrator, and the Metropolis decision of Algorithm 1.
@@ -33,6 +37,9 @@ gp_status hip_fail(hipError_t e, const char *where);
 namespace {
 
 constexpr int kHistMax = 20;
+constexpr int kCheck = 4;          // fixed-point iterations between host convergence checks
+constexpr int kTh = kMaxD + 4;     // stride of the theta / pi parts of the device state
+constexpr size_t kImpDoubles = 4 * kTh + 2 * (size_t)kHistMax * 2 * kTh + (size_t)kHistMax * kHistMax;
 constexpr int kDotBlocks = 512;
 // Transfer block of a fixed-point iteration: the force pass's gradient, the block partials of
 // |y - A(m) x|^2 and those of the new Gram row, fetched to the host together.
@@ -88,16 +95,6 @@ __global__ void fixed_point_x(int64_t n, const T *src, const T *x, double inv_c,
   gx[i] = (T)((double)x[i] + f);
 }
 
-// x = sum_j alpha_j G[j]
-template <typename T>
-__global__ void combine(int64_t n, int m, const double *alpha, const T *G, int64_t ldg, T *x) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < m; ++j) s += alpha[j] * (double)G[(int64_t)j * ldg + i];
-  x[i] = (T)s;
-}
-
 template <typename T>
 __global__ void scale_copy(int64_t n, const T *a, double s, T *b) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -106,7 +103,7 @@ __global__ void scale_copy(int64_t n, const T *a, double s, T *b) {
 
 struct ImpLayout {
   size_t qf, qf_bytes, pcg, pcg_bytes, Z, AZ, x, v, rb, fx, gx, Fh, Gh, part, alpha, grad, th0,
-      xf, wts, nys, total;
+      xf, wts, nys, ist, iflags, total;
 };
 
 ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
@@ -146,57 +143,225 @@ ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
   o += align256(sizeof(double) * (kMaxD + 4 + 2 + 8));
   L.th0 = o;
   o += align256(sizeof(double) * (kMaxD + 4));
-  L.xf = o;  // one device -> host transfer per fixed-point iteration (kXf* offsets)
+  L.xf = o;  // a fixed-point iteration's force, residual and Gram-row partials (kXf* offsets)
   o += align256(sizeof(double) * kXfDoubles);
   L.wts = o;
   o += align256(sizeof(double) * 2);
   L.nys = o;
   o += align256(rank > 0 ? nystrom_apply_scratch(n, rank, 1) : 0);
+  L.ist = o;
+  o += align256(sizeof(double) * kImpDoubles);
+  L.iflags = o;
+  o += align256(sizeof(int32_t) * 4);
   L.total = o;
   return L;
 }
 
-// Minimise |sum alpha_i f_i|^2 subject to sum alpha_i = 1 from the Gram matrix G (m x m):
-// alpha = G^{-1} 1 / (1^T G^{-1} 1), with a small ridge for a near-singular history.
-std::vector<double> anderson_weights(const std::vector<double> &G, int m) {
-  double tr = 0.0;
-  for (int i = 0; i < m; ++i) tr += G[(size_t)i * m + i];
-  std::vector<double> a((size_t)m * m), b(m, 1.0);
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) a[(size_t)i * m + j] = G[(size_t)i * m + j] + (i == j ? 1e-12 * tr / m : 0.0);
-  // Gaussian elimination with partial pivoting
+// Device state of the fixed-point iteration (double): the step's start (ths, pis), the current
+// iterate (th, pi), the parameter parts of the history's f and g ([kHistMax][2 kTh]) and its
+// Gram matrix ([kHistMax][kHistMax]); flags: [0] converged, [1] status bits, [2] iterations
+// taken, [3] the x update of the iteration (0 none, 1 Anderson combination, 2 x = g).
+struct ImpDev {
+  double *ths, *pis, *th, *pi, *hf, *hg, *G;
+  int32_t *flags;
+};
+
+// Minimise |sum alpha_i f_i|^2 subject to sum alpha_i = 1 from the Gram matrix a (LDS, m x m,
+// row stride kHistMax, overwritten): alpha = G^{-1} 1 / (1^T G^{-1} 1), with a small ridge for a
+// near-singular history; Gaussian elimination with partial pivoting (the pivot search and the
+// back substitution by lane 0, the row updates one row per lane).  A degenerate history gives
+// the plain fixed-point step (alpha = e_m).  One wave; b, z and alpha in LDS (kHistMax each).
+__device__ void anderson_weights(double *a, int m, double *b, double *z, double *alpha) {
+  const int t = threadIdx.x;
+  __shared__ int s_piv;
+  __shared__ double s_tr;
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < m; ++i) tr += a[i * kHistMax + i];
+    s_tr = tr;
+  }
+  __syncthreads();
+  if (t < m) {
+    a[t * kHistMax + t] += 1e-12 * s_tr / m;
+    b[t] = 1.0;
+  }
+  __syncthreads();
   for (int c = 0; c < m; ++c) {
-    int p = c;
-    for (int r = c + 1; r < m; ++r)
-      if (fabs(a[(size_t)r * m + c]) > fabs(a[(size_t)p * m + c])) p = r;
+    if (t == 0) {
+      int p = c;
+      for (int r = c + 1; r < m; ++r)
+        if (fabs(a[r * kHistMax + c]) > fabs(a[p * kHistMax + c])) p = r;
+      s_piv = p;
+    }
+    __syncthreads();
+    const int p = s_piv;
     if (p != c) {
-      for (int j = 0; j < m; ++j) std::swap(a[(size_t)c * m + j], a[(size_t)p * m + j]);
-      std::swap(b[c], b[p]);
+      if (t < m) {
+        const double u = a[c * kHistMax + t];
+        a[c * kHistMax + t] = a[p * kHistMax + t];
+        a[p * kHistMax + t] = u;
+      }
+      if (t == 0) {
+        const double u = b[c];
+        b[c] = b[p];
+        b[p] = u;
+      }
     }
-    const double d = a[(size_t)c * m + c];
-    if (fabs(d) < 1e-300) continue;
-    for (int r = c + 1; r < m; ++r) {
-      const double f = a[(size_t)r * m + c] / d;
-      for (int j = c; j < m; ++j) a[(size_t)r * m + j] -= f * a[(size_t)c * m + j];
-      b[r] -= f * b[c];
+    __syncthreads();
+    const double d = a[c * kHistMax + c];
+    if (fabs(d) >= 1e-300 && t > c && t < m) {
+      const double f = a[t * kHistMax + c] / d;
+      for (int j = c; j < m; ++j) a[t * kHistMax + j] -= f * a[c * kHistMax + j];
+      b[t] -= f * b[c];
     }
+    __syncthreads();
   }
-  std::vector<double> z(m, 0.0);
-  for (int r = m - 1; r >= 0; --r) {
-    double s = b[r];
-    for (int j = r + 1; j < m; ++j) s -= a[(size_t)r * m + j] * z[j];
-    const double d = a[(size_t)r * m + r];
-    z[r] = fabs(d) < 1e-300 ? 0.0 : s / d;
+  if (t == 0) {
+    for (int r = m - 1; r >= 0; --r) {
+      double u = b[r];
+      for (int j = r + 1; j < m; ++j) u -= a[r * kHistMax + j] * z[j];
+      const double d = a[r * kHistMax + r];
+      z[r] = fabs(d) < 1e-300 ? 0.0 : u / d;
+    }
+    double sum = 0.0;
+    for (int i = 0; i < m; ++i) sum += z[i];
+    const bool degenerate = !(fabs(sum) > 0.0) || !isfinite(sum);
+    for (int i = 0; i < m; ++i) alpha[i] = degenerate ? (i == m - 1 ? 1.0 : 0.0) : z[i] / sum;
   }
-  double sum = 0.0;
-  for (int i = 0; i < m; ++i) sum += z[i];
-  std::vector<double> alpha(m, 0.0);
-  if (!(fabs(sum) > 0.0) || !isfinite(sum)) {
-    alpha[m - 1] = 1.0;  // degenerate history: plain fixed-point step
-    return alpha;
+  __syncthreads();
+}
+
+// Start of a step: (ths, pis) = (th, pi), nothing converged yet.
+__global__ void imp_begin_step(ImpDev s, int nth) {
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < nth; ++k) {
+    s.ths[k] = s.th[k];
+    s.pis[k] = s.pi[k];
   }
-  for (int i = 0; i < m; ++i) alpha[i] = z[i] / sum;
-  return alpha;
+  s.flags[0] = 0;
+  s.flags[3] = 0;
+}
+
+// The midpoint (theta_0 + theta) / 2 at which the iteration's force pass runs.
+__global__ void imp_midpoint(ImpDev s, int nth, double *mid) {
+  const int k = threadIdx.x;
+  if (s.flags[0] || s.flags[1] || k >= nth) return;
+  mid[k] = 0.5 * (s.ths[k] + s.th[k]);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One fixed-point iteration's bookkeeping, one wave of 64 lanes working in LDS: g = Phi(v) and
+// f = g - v for the parameter parts from the force F (one component per lane), the convergence
+// test on f and on |y - A(m) x| (the block partials of its square), then the next iterate: g
+// (Picard, or the converged iteration's map value) or the Anderson combination over the last
+// m_new pairs (slot `head` just written; the x parts' Gram row arrives as block partials).
+__global__ __launch_bounds__(64) void imp_update(ImpDev s, int nth, double dt, double tol,
+                                                 double ynorm, int kh, int m_new, int head, int nb,
+                                                 const double *F, const double *res_part,
+                                                 const double *row_part, double *alpha_d) {
+  __shared__ double gtp[2 * kTh], ftp[2 * kTh];
+  __shared__ double a[kHistMax * kHistMax], b[kHistMax], z[kHistMax], alpha[kHistMax];
+  const int t = threadIdx.x;
+  if (s.flags[0] || s.flags[1]) {  // converged or failed: iterations after it change nothing
+    if (t == 0) s.flags[3] = 0;
+    return;
+  }
+  double fm = 0.0, vm = 0.0;
+  for (int k = t; k < nth; k += 64) {
+    const double th = s.th[k], pi = s.pi[k], ths = s.ths[k], pis = s.pis[k];
+    const double g0 = ths + dt * 0.5 * (pis + pi), g1 = pis - dt * F[k];
+    gtp[k] = g0;
+    gtp[nth + k] = g1;
+    ftp[k] = g0 - th;
+    ftp[nth + k] = g1 - pi;
+    const double af = fmax(fabs(g0 - th), fabs(g1 - pi)), av = fmax(fabs(th), fabs(pi));
+    fm = (af > fm || af != af) ? af : fm;  // a NaN propagates
+    vm = fmax(vm, av);
+  }
+  fm = wave_max(fm);
+  vm = wave_max(vm);
+  double rr2 = 0.0;
+  for (int q = t; q < nb; q += 64) rr2 += res_part[q];
+  rr2 = wave_sum(rr2);
+  __syncthreads();
+  if (!isfinite(fm)) {
+    if (t == 0) {
+      s.flags[1] |= GP_CHAIN_NONFINITE_THETA;
+      s.flags[3] = 0;
+      s.flags[2] += 1;
+    }
+    return;
+  }
+  const bool conv = fm <= tol * (1.0 + vm) && sqrt(rr2) <= tol * ynorm;
+  if (conv || kh == 0) {
+    for (int k = t; k < nth; k += 64) {
+      s.th[k] = gtp[k];
+      s.pi[k] = gtp[nth + k];
+    }
+    if (t == 0) {
+      s.flags[0] = conv ? 1 : 0;
+      s.flags[3] = conv ? 0 : 2;
+      s.flags[2] += 1;
+    }
+    return;
+  }
+  const int w = 2 * kTh;
+  double *hfh = s.hf + head * w;
+  for (int k = t; k < 2 * nth; k += 64) {
+    hfh[k] = ftp[k];
+    s.hg[head * w + k] = gtp[k];
+  }
+  // the new Gram row: lane j sums its x-part partials and the parameter parts' product
+  if (t < m_new) {
+    double u = 0.0;
+    for (int q = 0; q < nb; ++q) u += row_part[q * m_new + t];
+    const double *hfj = s.hf + t * w;
+    for (int k = 0; k < 2 * nth; ++k) u += ftp[k] * (t == head ? ftp[k] : hfj[k]);
+    s.G[head * kHistMax + t] = u;
+    s.G[t * kHistMax + head] = u;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int e = t; e < m_new * m_new; e += 64) {
+    const int i = e / m_new, j = e % m_new;
+    a[i * kHistMax + j] = s.G[i * kHistMax + j];
+  }
+  __syncthreads();
+  anderson_weights(a, m_new, b, z, alpha);
+  for (int k = t; k < nth; k += 64) {
+    double u = 0.0, v = 0.0;
+    for (int j = 0; j < m_new; ++j) {
+      u += alpha[j] * s.hg[j * w + k];
+      v += alpha[j] * s.hg[j * w + nth + k];
+    }
+    s.th[k] = u;
+    s.pi[k] = v;
+  }
+  if (t < m_new) alpha_d[t] = alpha[t];
+  if (t == 0) {
+    s.flags[3] = 1;
+    s.flags[2] += 1;
+  }
+}
+
+// x = sum_j alpha_j G[j] (Anderson), x = g (Picard), or unchanged, as imp_update decided.
+template <typename T>
+__global__ void imp_x_update(int64_t n, int m, const int32_t *flags, const double *alpha,
+                             const T *G, int64_t ldg, const T *gx, T *x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int mode = flags[3];
+  if (i >= n || mode == 0) return;
+  if (mode == 2) {
+    x[i] = gx[i];
+    return;
+  }
+  double t = 0.0;
+  for (int j = 0; j < m; ++j) t += alpha[j] * (double)G[(int64_t)j * ldg + i];
+  x[i] = (T)t;
 }
 
 template <typename T>
@@ -349,29 +514,42 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
   const double ynorm = sqrt(yy);
 
   std::vector<double> th = th0, pi = pi0;
-  std::vector<double> hf((size_t)kHistMax * 2 * nth), hg((size_t)kHistMax * 2 * nth);  // host parts
-  std::vector<double> G((size_t)kHistMax * kHistMax);
-  // One host round trip per fixed-point iteration: the midpoint theta and the Anderson weights
-  // go up without a wait (the host buffers are not touched again before the next transfer
-  // down, which follows them on the stream), and the device work of the iteration is enqueued
-  // whole before its one transfer down.
   const int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
   double *xf = (double *)(c.w + c.L.xf);
   double *wts_d = (double *)(c.w + c.L.wts);
   const double wts[2] = {-0.5, 0.5};
   st = h2d<T>(wts_d, wts, 2, c.s);
   if (st) return st;
-  std::vector<double> hx(kXfDoubles), mid(nth), alpha_h(kHistMax);
+  // the device state: (th, pi) = (theta_0, pi_0), nothing taken yet
+  double *ist = (double *)(c.w + c.L.ist);
+  ImpDev ds;
+  ds.ths = ist;
+  ds.pis = ist + kTh;
+  ds.th = ist + 2 * kTh;
+  ds.pi = ist + 3 * kTh;
+  ds.hf = ist + 4 * kTh;
+  ds.hg = ds.hf + (size_t)kHistMax * 2 * kTh;
+  ds.G = ds.hg + (size_t)kHistMax * 2 * kTh;
+  ds.flags = (int32_t *)(c.w + c.L.iflags);
+  {
+    std::vector<double> v0(2 * kTh, 0.0);
+    std::copy(th0.begin(), th0.end(), v0.begin());
+    std::copy(pi0.begin(), pi0.end(), v0.begin() + kTh);
+    e = hipMemcpyAsync(ds.th, v0.data(), sizeof(double) * 2 * kTh, hipMemcpyHostToDevice, c.s);
+    const int32_t f0[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(ds.flags, f0, sizeof(f0), hipMemcpyHostToDevice, c.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+    if (e != hipSuccess) return hip_fail(e, "fixed-point state");
+  }
+  int32_t fl[4] = {0, 0, 0, 0};
   for (int step = 0; step < p.n_steps && status == 0; ++step) {
-    const std::vector<double> ths = th, pis = pi;
-    int m = 0, head = 0;  // history size, next slot
-    bool conv = false;
-    // the current iterate v = (th, pi, x)
+    imp_begin_step<<<1, 64, 0, c.s>>>(ds, nth);
     for (int it = 0; it < p.maxit; ++it) {
-      ++total_it;
-      for (int kx = 0; kx < nth; ++kx) mid[kx] = 0.5 * (ths[kx] + th[kx]);
-      e = hipMemcpyAsync(c.thd, mid.data(), sizeof(double) * nth, hipMemcpyHostToDevice, c.s);
-      if (e != hipSuccess) return hip_fail(e, "host -> device");
+      // the history's size and slot follow from the iteration count alone (every iteration
+      // before convergence adds one pair); iterations after convergence are no-ops
+      const int m_new = kh > 0 ? std::min(it + 1, kh) : 0;
+      const int head = kh > 0 ? it % kh : 0;
+      imp_midpoint<<<1, kTh, 0, c.s>>>(ds, nth, c.thd);
       pack_z<T><<<gb, 256, 0, c.s>>>(n, x, c.phi, Z);
       st = gp_quadform_grad(c.k, n, c.X, c.thd, 2, Z, 2, Z, 2, wts_d, xf + kXfGrad, nullptr, AZ, 2,
                             nullptr, 0, c.w + c.L.qf, c.L.qf_bytes, c.s);
@@ -386,92 +564,35 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
       } else {
         fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, rb, x, inv_c, fx, gx);
       }
-      // Anderson history: (f, g) into slot `head` and the new Gram row, ahead of the host's
-      // convergence test (a converged iteration leaves them unused)
-      const int m_new = kh > 0 ? std::min(m + 1, kh) : 0;
-      if (kh > 0) {
+      if (kh > 0) {  // (f, g) of x into slot `head`, the x parts of the new Gram row
         e = hipMemcpyAsync(Fh + (size_t)head * n, fx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
         if (e == hipSuccess)
           e = hipMemcpyAsync(Gh + (size_t)head * n, gx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
         if (e != hipSuccess) return hip_fail(e, "history");
         multi_dot<T><<<nb, 256, 0, c.s>>>(n, m_new, fx, Fh, n, xf + kXfRow);
       }
+      imp_update<<<1, 64, 0, c.s>>>(ds, nth, p.dt, p.tol, ynorm, kh, m_new, head, nb, xf + kXfGrad,
+                                    xf + kXfRes, xf + kXfRow, alpha_d);
+      imp_x_update<T><<<gb, 256, 0, c.s>>>(n, m_new, ds.flags, alpha_d, Gh, n, gx, x);
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "fixed-point kernels");
-      st = d2h(hx.data(), xf, kXfRow + nb * m_new, c.s);
-      if (st) return st;
-      // g = Phi(v), f = g - v
-      const double *F = hx.data() + kXfGrad;
-      std::vector<double> g_tp(2 * nth), f_tp(2 * nth);
-      double fmax = 0.0, vmax = 0.0;
-      for (int kx = 0; kx < nth; ++kx) {
-        g_tp[kx] = ths[kx] + p.dt * 0.5 * (pis[kx] + pi[kx]);
-        g_tp[nth + kx] = pis[kx] - p.dt * F[kx];
-        f_tp[kx] = g_tp[kx] - th[kx];
-        f_tp[nth + kx] = g_tp[nth + kx] - pi[kx];
-        fmax = std::max(fmax, std::max(fabs(f_tp[kx]), fabs(f_tp[nth + kx])));
-        vmax = std::max(vmax, std::max(fabs(th[kx]), fabs(pi[kx])));
+      if ((it + 1) % kCheck == 0 || it + 1 == p.maxit) {
+        e = hipMemcpyAsync(fl, ds.flags, sizeof(fl), hipMemcpyDeviceToHost, c.s);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+        if (e != hipSuccess) return hip_fail(e, "convergence check");
+        if (fl[0] || fl[1]) break;
       }
-      if (!isfinite(fmax)) {
-        status |= GP_CHAIN_NONFINITE_THETA;
-        break;
-      }
-      double rr2 = 0.0;
-      for (int b = 0; b < nb; ++b) rr2 += hx[(size_t)kXfRes + b];
-      const double res = sqrt(rr2);  // |y - A(m) x|
-      if (fmax <= p.tol * (1.0 + vmax) && res <= p.tol * ynorm) {
-        conv = true;
-        // take the last map value: theta_1, pi_1 from g
-        for (int kx = 0; kx < nth; ++kx) {
-          th[kx] = g_tp[kx];
-          pi[kx] = g_tp[nth + kx];
-        }
-        break;
-      }
-      if (kh == 0) {  // Picard
-        for (int kx = 0; kx < nth; ++kx) {
-          th[kx] = g_tp[kx];
-          pi[kx] = g_tp[nth + kx];
-        }
-        e = hipMemcpyAsync(x, gx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
-        if (e != hipSuccess) return hip_fail(e, "copy");
-        continue;
-      }
-      // Anderson: the parameter parts of (f, g) in slot `head`, the Gram row, the combination
-      for (int kx = 0; kx < 2 * nth; ++kx) {
-        hf[(size_t)head * 2 * nth + kx] = f_tp[kx];
-        hg[(size_t)head * 2 * nth + kx] = g_tp[kx];
-      }
-      m = m_new;
-      for (int j = 0; j < m; ++j) {
-        double t = 0.0;
-        for (int b = 0; b < nb; ++b) t += hx[(size_t)kXfRow + (size_t)b * m + j];
-        for (int kx = 0; kx < 2 * nth; ++kx) t += hf[(size_t)head * 2 * nth + kx] * hf[(size_t)j * 2 * nth + kx];
-        G[(size_t)head * kHistMax + j] = t;
-        G[(size_t)j * kHistMax + head] = t;
-      }
-      std::vector<double> Gm((size_t)m * m);
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) Gm[(size_t)i * m + j] = G[(size_t)i * kHistMax + j];
-      const std::vector<double> alpha = anderson_weights(Gm, m);
-      for (int kx = 0; kx < nth; ++kx) {
-        double a = 0.0, b = 0.0;
-        for (int j = 0; j < m; ++j) {
-          a += alpha[j] * hg[(size_t)j * 2 * nth + kx];
-          b += alpha[j] * hg[(size_t)j * 2 * nth + nth + kx];
-        }
-        th[kx] = a;
-        pi[kx] = b;
-      }
-      std::copy(alpha.begin(), alpha.end(), alpha_h.begin());
-      e = hipMemcpyAsync(alpha_d, alpha_h.data(), sizeof(double) * m, hipMemcpyHostToDevice, c.s);
-      if (e != hipSuccess) return hip_fail(e, "host -> device");
-      combine<T><<<gb, 256, 0, c.s>>>(n, m, alpha_d, Gh, n, x);
-      e = hipGetLastError();
-      if (e != hipSuccess) return hip_fail(e, "Anderson combination");
-      head = (head + 1) % kh;
     }
-    if (!conv && status == 0) status |= GP_CHAIN_FP_MAXIT;
+    status |= fl[1];
+    if (!fl[0] && status == 0) status |= GP_CHAIN_FP_MAXIT;
+  }
+  total_it = fl[2];
+  {
+    std::vector<double> v1(2 * kTh);
+    st = d2h(v1.data(), ds.th, 2 * kTh, c.s);
+    if (st) return st;
+    std::copy(v1.begin(), v1.begin() + nth, th.begin());
+    std::copy(v1.begin() + kTh, v1.begin() + kTh + nth, pi.begin());
   }
 
   // end: solve at theta_1, H_1, Metropolis decision

@@ -666,7 +666,16 @@ __global__ __launch_bounds__(256) void finalise_xm(XArgs a, int has_grad) {
     double q = 0.0;
     if (live) {
       double ky = 0.0;
-      for (int s = 0; s < a.splits; ++s) ky += a.outp[((int64_t)s * a.n + i) * R + c];
+      // the split partials in split order, 8 loads in flight
+      for (int s0 = 0; s0 < a.splits; s0 += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          t[u] = s0 + u < a.splits ? a.outp[((int64_t)(s0 + u) * a.n + i) * R + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (s0 + u < a.splits) ky += t[u];
+      }
       const double yic = (double)a.Y[i * a.ldy + c];
       ky += alpha * yic;
       const double v = ky + (sigma2 + (a.col_shift ? a.col_shift[c] : 0.0)) * yic;
