@@ -334,7 +334,7 @@ _HMC_WS = {}
 
 
 def _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chains, dims,
-                 x_offsets, n_cheb, pi_name="pi"):
+                 x_offsets, n_cheb, pi_name="pi", phi_name="phi", xw_name="x_warm"):
     """Lengths of the packed arrays against the batch description (packing of include/gpk.h)."""
     n_inst = len(n_points)
     if n_inst < 1 or len(offsets) != n_inst or len(dims) != n_inst:
@@ -356,8 +356,8 @@ def _check_batch(X, y, phi, theta, pi, x_warm, u, kind, n_points, offsets, chain
         nth_total += n_theta(kind, db, n_cheb)
     _len_at_least(X, need_x, "X")
     _len_at_least(y, need_y, "y")
-    _len_at_least(phi, need_v, "phi")
-    _len_at_least(x_warm, need_v, "x_warm")
+    _len_at_least(phi, need_v, phi_name)
+    _len_at_least(x_warm, need_v, xw_name)
     _len_at_least(theta, int(chains) * nth_total, "theta")
     _len_at_least(pi, int(chains) * nth_total, pi_name)
     _len_at_least(u, n_inst * int(chains), "u")
@@ -623,7 +623,7 @@ def phi_refresh_chains(X, theta, xi, kind, n_points, offsets, chains, d=None, x_
     n_inst = len(n_points)
     dims = [X.shape[1]] * n_inst if d is None else list(d)
     _check_batch(X, None, xi, theta, None, out, None, kind, n_points, offsets, chains, dims,
-                 x_offsets, n_cheb)
+                 x_offsets, n_cheb, phi_name="xi", xw_name="out")
     k = Kernel(kind_code(kind), prec_code(dt_, prec), int(max(dims)), 0, int(n_cheb))
     prm = PhiParams(int(n_poles), float(tol), int(maxit), float(lambda_max or 0.0), 0, None, None)
     npts = (ctypes.c_int64 * n_inst)(*[int(v) for v in n_points])

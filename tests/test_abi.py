@@ -352,6 +352,29 @@ def test_binding_rejects_mis_sized_trajectory_arguments():
         gpk.hmc_implicit(X, y[:50], phi[:50], _t(3, dtype=f64), _t(2, dtype=f64), xw[:50])
 
 
+def test_binding_rejects_mis_sized_refresh_arguments():
+    import torch
+    f64 = torch.float64
+    ns, offs, chains = [30, 20], [0, 30], 3
+    X, xi, th = _t(50, 2), _t(150), _t(18, dtype=f64)
+
+    def call(**kw):
+        a = dict(X=X, xi=xi, theta=th, out=None)
+        a.update(kw)
+        return gpk.phi_refresh_chains(a["X"], a["theta"], a["xi"], "iso", ns, offs, chains,
+                                      out=a["out"])
+    with pytest.raises(ValueError, match="GPU"):
+        call()
+    for name, bad in (("X", _t(49, 2)), ("xi", _t(149)), ("theta", _t(17, dtype=f64)),
+                      ("out", _t(149))):
+        with pytest.raises(ValueError, match=name):
+            call(**{name: bad})
+    with pytest.raises(TypeError, match="theta"):
+        call(theta=_t(18))
+    with pytest.raises(TypeError, match="out"):
+        call(out=_t(150, dtype=f64))
+
+
 def test_kmatvec_noalloc_validates_before_any_hip_call():
     # argument errors and a workspace that cannot fit the library's 64 MiB array are reported
     # with no HIP call (so this runs on a CPU-only host); empty products succeed
