@@ -50,8 +50,25 @@ constexpr int kXfDoubles = kXfRow + kDotBlocks * kHistMax;
 
 // out[b][j] = partial sums over this block's rows of a[i] * H[j][i] for j < m (H rows of length n)
 template <typename T>
+__device__ void multi_dot_body(int64_t n, int m, const T *a, const T *H, int64_t ldh, double *out);
+
+template <typename T>
 __global__ __launch_bounds__(256) void multi_dot(int64_t n, int m, const T *a, const T *H,
                                                  int64_t ldh, double *out) {
+  multi_dot_body<T>(n, m, a, H, ldh, out);
+}
+
+// The Gram row of the fixed-point iteration: m = min(it + 1, kh) rows, it = flags[4] the
+// iteration's index within its step.
+template <typename T>
+__global__ __launch_bounds__(256) void multi_dot_hist(int64_t n, const int32_t *flags, int kh,
+                                                      const T *a, const T *H, int64_t ldh,
+                                                      double *out) {
+  multi_dot_body<T>(n, min(flags[4] + 1, kh), a, H, ldh, out);
+}
+
+template <typename T>
+__device__ void multi_dot_body(int64_t n, int m, const T *a, const T *H, int64_t ldh, double *out) {
   __shared__ double sh[4][kHistMax + 1];
   double acc[kHistMax + 1];
   for (int j = 0; j < m; ++j) acc[j] = 0.0;
@@ -152,7 +169,7 @@ ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
   L.ist = o;
   o += align256(sizeof(double) * kImpDoubles);
   L.iflags = o;
-  o += align256(sizeof(int32_t) * 4);
+  o += align256(sizeof(int32_t) * 8);
   L.total = o;
   return L;
 }
@@ -160,7 +177,9 @@ ImpLayout imp_layout(const gp_kernel *k, int64_t n, int hist, int rank) {
 // Device state of the fixed-point iteration (double): the step's start (ths, pis), the current
 // iterate (th, pi), the parameter parts of the history's f and g ([kHistMax][2 kTh]) and its
 // Gram matrix ([kHistMax][kHistMax]); flags: [0] converged, [1] status bits, [2] iterations
-// taken, [3] the x update of the iteration (0 none, 1 Anderson combination, 2 x = g).
+// taken, [3] the x update of the iteration (0 none, 1 Anderson combination, 2 x = g), [4] the
+// iteration's index within its step (the history holds min(it + 1, k) pairs, the newest in slot
+// it mod k), so that every iteration enqueues the same launches.
 struct ImpDev {
   double *ths, *pis, *th, *pi, *hf, *hg, *G;
   int32_t *flags;
@@ -240,6 +259,18 @@ __global__ void imp_begin_step(ImpDev s, int nth) {
   }
   s.flags[0] = 0;
   s.flags[3] = 0;
+  s.flags[4] = 0;
+}
+
+// (f, g) of x into the history slot of this iteration.
+template <typename T>
+__global__ void hist_store(int64_t n, const int32_t *flags, int kh, const T *fx, const T *gx, T *Fh,
+                           T *Gh) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = (int64_t)(flags[4] % kh) * n + i;
+  Fh[o] = fx[i];
+  Gh[o] = gx[i];
 }
 
 // The midpoint (theta_0 + theta) / 2 at which the iteration's force pass runs.
@@ -260,16 +291,21 @@ __device__ __forceinline__ double wave_max(double v) {
 // (Picard, or the converged iteration's map value) or the Anderson combination over the last
 // m_new pairs (slot `head` just written; the x parts' Gram row arrives as block partials).
 __global__ __launch_bounds__(64) void imp_update(ImpDev s, int nth, double dt, double tol,
-                                                 double ynorm, int kh, int m_new, int head, int nb,
+                                                 double ynorm, int kh, int maxit, int nb,
                                                  const double *F, const double *res_part,
                                                  const double *row_part, double *alpha_d) {
   __shared__ double gtp[2 * kTh], ftp[2 * kTh];
   __shared__ double a[kHistMax * kHistMax], b[kHistMax], z[kHistMax], alpha[kHistMax];
   const int t = threadIdx.x;
-  if (s.flags[0] || s.flags[1]) {  // converged or failed: iterations after it change nothing
+  const int it = s.flags[4];
+  __syncthreads();  // every lane has read the index before lane 0 advances it
+  if (t == 0) s.flags[4] = it + 1;
+  // converged, failed or past the iteration limit: iterations after it change nothing
+  if (s.flags[0] || s.flags[1] || it >= maxit) {
     if (t == 0) s.flags[3] = 0;
     return;
   }
+  const int m_new = kh > 0 ? min(it + 1, kh) : 0, head = kh > 0 ? it % kh : 0;
   double fm = 0.0, vm = 0.0;
   for (int k = t; k < nth; k += 64) {
     const double th = s.th[k], pi = s.pi[k], ths = s.ths[k], pis = s.pis[k];
@@ -348,12 +384,14 @@ __global__ __launch_bounds__(64) void imp_update(ImpDev s, int nth, double dt, d
   }
 }
 
-// x = sum_j alpha_j G[j] (Anderson), x = g (Picard), or unchanged, as imp_update decided.
+// x = sum_j alpha_j G[j] (Anderson, over the min(it + 1, kh) pairs of the iteration just
+// taken), x = g (Picard), or unchanged, as imp_update decided.
 template <typename T>
-__global__ void imp_x_update(int64_t n, int m, const int32_t *flags, const double *alpha,
+__global__ void imp_x_update(int64_t n, int kh, const int32_t *flags, const double *alpha,
                              const T *G, int64_t ldg, const T *gx, T *x) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int mode = flags[3];
+  const int m = min(flags[4], kh);  // imp_update has advanced the index past this iteration
   if (i >= n || mode == 0) return;
   if (mode == 2) {
     x[i] = gx[i];
@@ -536,56 +574,75 @@ gp_status run_implicit(Ctx<T> &c, double *theta_d, double *pi_d, T *x_warm, cons
     std::copy(th0.begin(), th0.end(), v0.begin());
     std::copy(pi0.begin(), pi0.end(), v0.begin() + kTh);
     e = hipMemcpyAsync(ds.th, v0.data(), sizeof(double) * 2 * kTh, hipMemcpyHostToDevice, c.s);
-    const int32_t f0[4] = {0, 0, 0, 0};
+    const int32_t f0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(ds.flags, f0, sizeof(f0), hipMemcpyHostToDevice, c.s);
     if (e == hipSuccess) e = hipStreamSynchronize(c.s);
     if (e != hipSuccess) return hip_fail(e, "fixed-point state");
   }
-  int32_t fl[4] = {0, 0, 0, 0};
-  for (int step = 0; step < p.n_steps && status == 0; ++step) {
-    imp_begin_step<<<1, 64, 0, c.s>>>(ds, nth);
-    for (int it = 0; it < p.maxit; ++it) {
-      // the history's size and slot follow from the iteration count alone (every iteration
-      // before convergence adds one pair); iterations after convergence are no-ops
-      const int m_new = kh > 0 ? std::min(it + 1, kh) : 0;
-      const int head = kh > 0 ? it % kh : 0;
-      imp_midpoint<<<1, kTh, 0, c.s>>>(ds, nth, c.thd);
-      pack_z<T><<<gb, 256, 0, c.s>>>(n, x, c.phi, Z);
-      st = gp_quadform_grad(c.k, n, c.X, c.thd, 2, Z, 2, Z, 2, wts_d, xf + kXfGrad, nullptr, AZ, 2,
-                            nullptr, 0, c.w + c.L.qf, c.L.qf_bytes, c.s);
-      if (st) return st;
-      linear_residual<T><<<gb, 256, 0, c.s>>>(n, c.y, AZ, rb);
-      multi_dot<T><<<nb, 256, 0, c.s>>>(n, 1, rb, rb, n, xf + kXfRes);
-      if (c.rank > 0) {
-        e = nystrom_apply<T>(n, c.rank, (const T *)c.U, c.lam, th0_d, nth, nullptr, 1, rb, fx,
-                             c.w + c.L.nys, c.s);
-        if (e != hipSuccess) return hip_fail(e, "Nystrom apply");
-        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, fx, x, inv_c, fx, gx);
-      } else {
-        fixed_point_x<T><<<gb, 256, 0, c.s>>>(n, rb, x, inv_c, fx, gx);
-      }
-      if (kh > 0) {  // (f, g) of x into slot `head`, the x parts of the new Gram row
-        e = hipMemcpyAsync(Fh + (size_t)head * n, fx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(Gh + (size_t)head * n, gx, sizeof(T) * n, hipMemcpyDeviceToDevice, c.s);
-        if (e != hipSuccess) return hip_fail(e, "history");
-        multi_dot<T><<<nb, 256, 0, c.s>>>(n, m_new, fx, Fh, n, xf + kXfRow);
-      }
-      imp_update<<<1, 64, 0, c.s>>>(ds, nth, p.dt, p.tol, ynorm, kh, m_new, head, nb, xf + kXfGrad,
-                                    xf + kXfRes, xf + kXfRow, alpha_d);
-      imp_x_update<T><<<gb, 256, 0, c.s>>>(n, m_new, ds.flags, alpha_d, Gh, n, gx, x);
-      e = hipGetLastError();
-      if (e != hipSuccess) return hip_fail(e, "fixed-point kernels");
-      if ((it + 1) % kCheck == 0 || it + 1 == p.maxit) {
-        e = hipMemcpyAsync(fl, ds.flags, sizeof(fl), hipMemcpyDeviceToHost, c.s);
-        if (e == hipSuccess) e = hipStreamSynchronize(c.s);
-        if (e != hipSuccess) return hip_fail(e, "convergence check");
-        if (fl[0] || fl[1]) break;
-      }
+  // kCheck iterations, each the same launches (the history's size and slot and the iteration
+  // limit are read on the device), captured once as a graph and replayed between host checks
+  auto enqueue_iteration = [&](hipStream_t q) -> gp_status {
+    imp_midpoint<<<1, kTh, 0, q>>>(ds, nth, c.thd);
+    pack_z<T><<<gb, 256, 0, q>>>(n, x, c.phi, Z);
+    gp_status r = gp_quadform_grad(c.k, n, c.X, c.thd, 2, Z, 2, Z, 2, wts_d, xf + kXfGrad, nullptr,
+                                   AZ, 2, nullptr, 0, c.w + c.L.qf, c.L.qf_bytes, q);
+    if (r) return r;
+    linear_residual<T><<<gb, 256, 0, q>>>(n, c.y, AZ, rb);
+    multi_dot<T><<<nb, 256, 0, q>>>(n, 1, rb, rb, n, xf + kXfRes);
+    hipError_t he = hipSuccess;
+    if (c.rank > 0) {
+      he = nystrom_apply<T>(n, c.rank, (const T *)c.U, c.lam, th0_d, nth, nullptr, 1, rb, fx,
+                            c.w + c.L.nys, q);
+      if (he != hipSuccess) return hip_fail(he, "Nystrom apply");
+      fixed_point_x<T><<<gb, 256, 0, q>>>(n, fx, x, inv_c, fx, gx);
+    } else {
+      fixed_point_x<T><<<gb, 256, 0, q>>>(n, rb, x, inv_c, fx, gx);
     }
+    if (kh > 0) {  // (f, g) of x into the iteration's slot, the x parts of the new Gram row
+      hist_store<T><<<gb, 256, 0, q>>>(n, ds.flags, kh, fx, gx, Fh, Gh);
+      multi_dot_hist<T><<<nb, 256, 0, q>>>(n, ds.flags, kh, fx, Fh, n, xf + kXfRow);
+    }
+    imp_update<<<1, 64, 0, q>>>(ds, nth, p.dt, p.tol, ynorm, kh, p.maxit, nb, xf + kXfGrad,
+                                xf + kXfRes, xf + kXfRow, alpha_d);
+    imp_x_update<T><<<gb, 256, 0, q>>>(n, kh, ds.flags, alpha_d, Gh, n, gx, x);
+    he = hipGetLastError();
+    return he == hipSuccess ? GP_OK : hip_fail(he, "fixed-point kernels");
+  };
+  hipGraphExec_t exec = nullptr;
+  {
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t graph = nullptr;
+    gp_status sc = GP_OK;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < kCheck && sc == GP_OK; ++i) sc = enqueue_iteration(cap);
+      const hipError_t ee = hipStreamEndCapture(cap, &graph);
+      if (e == hipSuccess) e = ee;
+    }
+    if (e == hipSuccess && sc == GP_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (sc != GP_OK) return sc;
+    if (e != hipSuccess) return hip_fail(e, "fixed-point graph");
+  }
+  int32_t fl[5] = {0, 0, 0, 0, 0};
+  for (int step = 0; step < p.n_steps && status == 0 && st == GP_OK; ++step) {
+    imp_begin_step<<<1, 64, 0, c.s>>>(ds, nth);
+    e = hipGetLastError();
+    for (int it = 0; it < p.maxit && e == hipSuccess; it += kCheck) {
+      e = hipGraphLaunch(exec, c.s);
+      if (e == hipSuccess) e = hipMemcpyAsync(fl, ds.flags, sizeof(fl), hipMemcpyDeviceToHost, c.s);
+      if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+      if (e == hipSuccess && (fl[0] || fl[1])) break;
+    }
+    if (e != hipSuccess) break;
     status |= fl[1];
     if (!fl[0] && status == 0) status |= GP_CHAIN_FP_MAXIT;
   }
+  (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return hip_fail(e, "fixed-point iterations");
   total_it = fl[2];
   {
     std::vector<double> v1(2 * kTh);
