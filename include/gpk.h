@@ -484,8 +484,10 @@ gp_status gp_pcg_solve(const gp_kernel *k, int64_t n, const void *X, const doubl
  * (theta, pi) update is below tol (max norm, relative to 1 + |(theta, pi)|) and
  * |y - A(m) x| <= tol |y|.  The energies use solves at theta_0 and theta_1 by gp_pcg_solve
  * (Nystrom-preconditioned when rank > 0) and the variational form of y^T A^{-1} y; the
- * Metropolis decision is that of Algorithm 1.  The host drives the iteration; the call
- * synchronises `stream`.
+ * Metropolis decision is that of Algorithm 1.  The fixed-point iteration runs on the device
+ * (the Anderson least-squares problem included) as a captured graph of four iterations, which
+ * the host replays and checks for convergence after each replay; the call synchronises
+ * `stream`.
  *   X, y, phi     device, n x d / n / n, kernel precision
  *   theta, pi     device double[n_theta], in/out (accepted state or the start state); theta is
  *                 also used as scratch during the call

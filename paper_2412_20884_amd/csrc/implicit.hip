@@ -13,9 +13,9 @@
 // iteration).  Everything of an iteration runs on the device: the (theta, pi) parts and the
 // history's Gram matrix in double in a small state block, the convergence test, the
 // least-squares weights and the combination in one single-workgroup kernel (imp_update), the x
-// parts in the streaming kernels below.  The host enqueues iterations without waiting and reads
-// the state's convergence flag every kCheck iterations (iterations enqueued after convergence
-// change nothing).  c comes from power iterations
+// parts in the streaming kernels below.  Every iteration enqueues the same launches, so kCheck
+// of them are captured once per trajectory as a graph, which the host replays, reading the
+// state's convergence flag after each replay (iterations after convergence change nothing).  c comes from power iterations
 // on A(theta_0) (ten in the paper); with a Nystrom factor R = P^{-1} / c, P the preconditioner of
 // A(theta_0) and c ~ rho(P^{-1} A(theta_0)).  The trajectory ends with a solve at theta_1 for the energy,
 // as for the leapfrog integrator, and the Metropolis decision of Algorithm 1.
