@@ -14,8 +14,8 @@
 // A shifted system is frozen once its residual |zeta_p| |r| falls below tol |xi|; the smallest
 // shift is positive, so every shifted system converges no later than the unshifted one.
 //
-// The host drives the iteration and checks for convergence every few iterations (the call
-// synchronises its stream).  Scalars are kept in double on the device; vectors are in the
+// The host replays a captured graph of a few iterations and checks for convergence after each
+// replay (the call synchronises its stream).  Scalars are kept in double on the device; vectors are in the
 // precision of the products (float for GP_F32 and GP_BF16X, double for GP_F64).
 #include <math.h>
 #include <string.h>
@@ -550,24 +550,58 @@ gp_status run_phi(const gp_kernel *k, const gp_phi_params *pp, int64_t n, const 
   phi_setup<<<1, kThreads, 0, stream>>>(r, np, g.blocks, part, col, shf, remaining);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "phi set-up");
-  for (int it = 0; it < pp->maxit; ++it) {
-    if (it % kCheckEvery == 0) {
-      int32_t left = 0;
-      e = hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(stream);
-      if (e != hipSuccess) return hip_fail(e, "convergence check");
-      if (left == 0) break;
+  // one iteration: the same launches every time (finished columns skip their updates), so
+  // kCheckEvery of them are captured once as a graph and replayed between convergence checks;
+  // the iterations past the last whole group run eagerly, so no more than maxit are taken
+  auto iteration = [&](hipStream_t q) -> gp_status {
+    gp_status r2 = gp_kmatvec(k, n, X, theta, r, pv, r, nullptr, qv, r, prod, L.prod_bytes, q);
+    if (r2) return r2;
+    phi_dot<T><<<vb, kThreads, 0, q>>>(n, r, g, pv, qv, part);
+    phi_scalars_a<<<1, kThreads, 0, q>>>(r, np, g.blocks, part, wl, wl + np, col, shf);
+    phi_update<T><<<vb, kThreads, sizeof(double) * (3 * r * np + r), q>>>(n, r, np, g, col, shf, ps, rv, qv, phi, ldphi, part);
+    phi_scalars_b<<<1, kThreads, 0, q>>>(r, np, g.blocks, part, pp->tol, col, shf, remaining);
+    phi_direction<T><<<vb, kThreads, 0, q>>>(n, r, g, col, rv, pv);
+    const hipError_t he = hipGetLastError();
+    return he == hipSuccess ? GP_OK : hip_fail(he, "multi-shift CG iteration");
+  };
+  hipGraphExec_t exec = nullptr;
+  if (pp->maxit >= kCheckEvery) {
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t graph = nullptr;
+    gp_status sc = GP_OK;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < kCheckEvery && sc == GP_OK; ++i) sc = iteration(cap);
+      const hipError_t ee = hipStreamEndCapture(cap, &graph);
+      if (e == hipSuccess) e = ee;
     }
-    st = gp_kmatvec(k, n, X, theta, r, pv, r, nullptr, qv, r, prod, L.prod_bytes, stream);
-    if (st) return st;
-    phi_dot<T><<<vb, kThreads, 0, stream>>>(n, r, g, pv, qv, part);
-    phi_scalars_a<<<1, kThreads, 0, stream>>>(r, np, g.blocks, part, wl, wl + np, col, shf);
-    phi_update<T><<<vb, kThreads, sizeof(double) * (3 * r * np + r), stream>>>(n, r, np, g, col, shf, ps, rv, qv, phi, ldphi, part);
-    phi_scalars_b<<<1, kThreads, 0, stream>>>(r, np, g.blocks, part, pp->tol, col, shf, remaining);
-    phi_direction<T><<<vb, kThreads, 0, stream>>>(n, r, g, col, rv, pv);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "multi-shift CG iteration");
+    if (e == hipSuccess && sc == GP_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (sc != GP_OK) return sc;
+    if (e != hipSuccess) return hip_fail(e, "multi-shift CG graph");
   }
+  for (int it = 0; it < pp->maxit;) {
+    int32_t left = 0;
+    e = hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) break;
+    if (left == 0) break;
+    if (exec && pp->maxit - it >= kCheckEvery) {
+      e = hipGraphLaunch(exec, stream);
+      if (e != hipSuccess) break;
+      it += kCheckEvery;
+    } else {
+      st = iteration(stream);
+      if (st) break;
+      ++it;
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(e, "multi-shift CG");
   phi_finish<<<1, 64, 0, stream>>>(r, col, status, iters);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
