@@ -597,12 +597,14 @@ __global__ void pcg_scalars(int stage, int r, int64_t blocks, const double *part
             s.done = 1;
           }
         } else if (stage == 2) {
+          // iterations taken: `it` is 1 inside an iteration, 0 for the set-up's test (the
+          // launches carry no iteration index, so a captured group of them can be replayed)
+          s.iters += it;
           if (!isfinite(v)) {
             s.status |= GP_CG_NONFINITE;
             s.done = 1;
           } else if (v <= tol * tol * s.bb) {
             s.done = 1;
-            s.iters = it;
           }
         } else if (stage == 3) {
           s.beta = v / s.rz;
@@ -681,13 +683,13 @@ gp_status run_pcg(const gp_kernel *k, int64_t n, const void *X, const double *th
   const VecGrid g = vec_grid(n, r);
   const unsigned vb = (unsigned)g.blocks;
   const unsigned eb = (unsigned)((n * r + 255) / 256);
-  auto precond = [&]() -> gp_status {  // z = P^{-1} r
+  auto precond = [&](hipStream_t q) -> gp_status {  // z = P^{-1} r
     hipError_t e;
     if (rank == 0) {
-      copy_block<T><<<eb, 256, 0, s>>>(n, r, rv, zv);
+      copy_block<T><<<eb, 256, 0, q>>>(n, r, rv, zv);
       e = hipGetLastError();
     } else {
-      e = nystrom_apply<T>(n, rank, U, lam, theta, nth, shift, r, rv, zv, w + L.scr, s);
+      e = nystrom_apply<T>(n, rank, U, lam, theta, nth, shift, r, rv, zv, w + L.scr, q);
     }
     return e == hipSuccess ? GP_OK : hip_fail(e, "preconditioner");
   };
@@ -698,35 +700,71 @@ gp_status run_pcg(const gp_kernel *k, int64_t n, const void *X, const double *th
   pcg_scalars<<<1, 256, 0, s>>>(0, r, g.blocks, part, tol, 0, col, nullptr);
   pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, rv, part);
   pcg_scalars<<<1, 256, 0, s>>>(2, r, g.blocks, part, tol, 0, col, remaining);
-  st = precond();
+  st = precond(s);
   if (st) return st;
   pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, zv, part);
   pcg_scalars<<<1, 256, 0, s>>>(4, r, g.blocks, part, tol, 0, col, nullptr);
   pcg_direction<T><<<vb, 256, 0, s>>>(n, r, g, col, zv, pv, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "PCG set-up");
-  for (int it = 1; it <= maxit; ++it) {
-    if ((it - 1) % kCheckEvery == 0) {
-      int32_t left = 0;
-      e = hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_fail(e, "convergence check");
-      if (left == 0) break;
+  // one iteration: the same launches every time (finished columns skip their updates), so
+  // kCheckEvery of them are captured once as a graph and replayed between convergence checks;
+  // the iterations past the last whole group run eagerly, so no more than maxit are taken
+  auto iteration = [&](hipStream_t q) -> gp_status {
+    gp_status r2 = gp_kmatvec(k, n, X, theta, r, pv, r, shift, qv, r, w + L.prod, L.prod_bytes, q);
+    if (r2 == GP_OK) {
+      pcg_dot<T><<<vb, 256, 0, q>>>(n, r, g, pv, qv, part);
+      pcg_scalars<<<1, 256, 0, q>>>(1, r, g.blocks, part, tol, 0, col, nullptr);
+      pcg_update<T><<<vb, 256, 0, q>>>(n, r, g, col, pv, qv, x, ldx, rv, part);
+      pcg_scalars<<<1, 256, 0, q>>>(2, r, g.blocks, part, tol, 1, col, remaining);
+      r2 = precond(q);
     }
-    st = gp_kmatvec(k, n, X, theta, r, pv, r, shift, qv, r, w + L.prod, L.prod_bytes, s);
-    if (st) return st;
-    pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, pv, qv, part);
-    pcg_scalars<<<1, 256, 0, s>>>(1, r, g.blocks, part, tol, it, col, nullptr);
-    pcg_update<T><<<vb, 256, 0, s>>>(n, r, g, col, pv, qv, x, ldx, rv, part);
-    pcg_scalars<<<1, 256, 0, s>>>(2, r, g.blocks, part, tol, it, col, remaining);
-    st = precond();
-    if (st) return st;
-    pcg_dot<T><<<vb, 256, 0, s>>>(n, r, g, rv, zv, part);
-    pcg_scalars<<<1, 256, 0, s>>>(3, r, g.blocks, part, tol, it, col, nullptr);
-    pcg_direction<T><<<vb, 256, 0, s>>>(n, r, g, col, zv, pv, 0);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "PCG iteration");
+    if (r2 == GP_OK) {
+      pcg_dot<T><<<vb, 256, 0, q>>>(n, r, g, rv, zv, part);
+      pcg_scalars<<<1, 256, 0, q>>>(3, r, g.blocks, part, tol, 0, col, nullptr);
+      pcg_direction<T><<<vb, 256, 0, q>>>(n, r, g, col, zv, pv, 0);
+      const hipError_t he = hipGetLastError();
+      if (he != hipSuccess) r2 = hip_fail(he, "PCG iteration");
+    }
+    return r2;
+  };
+  hipGraphExec_t exec = nullptr;
+  if (maxit >= kCheckEvery) {
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    hipGraph_t graph = nullptr;
+    gp_status sc = GP_OK;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < kCheckEvery && sc == GP_OK; ++i) sc = iteration(cap);
+      const hipError_t ee = hipStreamEndCapture(cap, &graph);
+      if (e == hipSuccess) e = ee;
+    }
+    if (e == hipSuccess && sc == GP_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (sc != GP_OK) return sc;
+    if (e != hipSuccess) return hip_fail(e, "PCG graph");
   }
+  for (int it = 0; it < maxit;) {
+    int32_t left = 0;
+    e = hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || left == 0) break;
+    if (exec && maxit - it >= kCheckEvery) {
+      e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) break;
+      it += kCheckEvery;
+    } else {
+      st = iteration(s);
+      if (st) break;
+      ++it;
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(e, "PCG iterations");
   pcg_finish<<<1, 64, 0, s>>>(r, maxit, col, status, iters);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
