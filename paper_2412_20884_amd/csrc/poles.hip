@@ -106,11 +106,12 @@ __global__ void __launch_bounds__(kThreads) phi_dot(int64_t n, int r, VecGrid g,
 __global__ void phi_setup(int r, int np, int64_t blocks, const double *part, PoleCol *col,
                           PoleShift *sh, int32_t *remaining) {
   __shared__ double red[kThreads];
+  __shared__ double tot[kPhiMaxR];
   __shared__ int32_t left;
   if (threadIdx.x == 0) left = 0;
-  __syncthreads();
+  column_totals(part, blocks, r, red, tot);
   for (int c = 0; c < r; ++c) {
-    const double rr0 = column_total(part, blocks, r, c, red);
+    const double rr0 = tot[c];
     if (threadIdx.x == 0) {
       PoleCol s;
       s.rr = rr0;
@@ -148,8 +149,10 @@ __global__ void phi_scalars_a(int r, int np, int64_t blocks, const double *part,
                               const double *w, const double *lam, PoleCol *col, PoleShift *sh) {
   __shared__ double red[kThreads];
   __shared__ double a_sh[kPhiMaxR];
+  __shared__ double tot[kPhiMaxR];
+  column_totals(part, blocks, r, red, tot);
   for (int c = 0; c < r; ++c) {
-    const double pq = column_total(part, blocks, r, c, red);
+    const double pq = tot[c];
     if (threadIdx.x == 0) {
       PoleCol s = col[c];
       double a = 0.0;
@@ -245,8 +248,10 @@ __global__ void phi_scalars_b(int r, int np, int64_t blocks, const double *part,
   __shared__ double red[kThreads];
   __shared__ double rn_sh[kPhiMaxR];
   __shared__ int32_t alive[kPhiMaxR];
+  __shared__ double tot[kPhiMaxR];
+  column_totals(part, blocks, r, red, tot);
   for (int c = 0; c < r; ++c) {
-    const double rn = column_total(part, blocks, r, c, red);
+    const double rn = tot[c];
     if (threadIdx.x == 0) {
       rn_sh[c] = rn;
       alive[c] = 0;

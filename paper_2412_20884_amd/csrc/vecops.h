@@ -43,6 +43,28 @@ __device__ inline void block_column_sum(double v, double *sh, int r, int rps, do
 }
 
 // Fixed-order sum of part[b * r + c] over the blocks, by all threads of the (single) block.
+// Totals of every column c < r (r <= blockDim.x) of part[blocks][r] into tot[c] (LDS): G groups
+// of r threads each sum every G-th block, then a pairwise tree over the groups; the order
+// depends on blocks and r only.  red: blockDim.x doubles of LDS.
+__device__ inline void column_totals(const double *part, int64_t blocks, int r, double *red,
+                                     double *tot) {
+  const int t = threadIdx.x;
+  int G = 1;
+  while (2 * G * r <= (int)blockDim.x) G *= 2;
+  const int g = t / r, c = t - g * r;
+  double s = 0.0;
+  if (g < G)
+    for (int64_t b = g; b < blocks; b += G) s += part[b * r + c];
+  red[t] = s;
+  __syncthreads();
+  for (int h = G / 2; h > 0; h /= 2) {
+    if (g < h) red[t] += red[t + h * r];
+    __syncthreads();
+  }
+  if (t < r) tot[t] = red[t];
+  __syncthreads();
+}
+
 __device__ inline double column_total(const double *part, int64_t blocks, int r, int c, double *red) {
   const int t = threadIdx.x;
   double s = 0.0;
