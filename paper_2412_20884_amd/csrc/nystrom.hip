@@ -139,22 +139,26 @@ __global__ void gram_final(int nchunk, int64_t m, const double *part, double *G)
 template <typename T>
 __global__ __launch_bounds__(256) void right_mul(int64_t n, int l, const T *A, int64_t lda,
                                                  const double *M, int m, const T *Cin,
-                                                 int64_t ldc, T *out, int64_t ldo) {
+                                                 int64_t ldc, T *out, int64_t ldo, int kper,
+                                                 double *part) {
   __shared__ double sa[kMR][kMK + 1], sm[kMK][kMC + 1];
   const int t = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * kMR;
   const int c0 = blockIdx.y * kMC;
   const int rr = t / 4, cc = (t % 4) * 8;
+  // split over the inner dimension (gridDim.z > 1): this block's kper of the l terms, its
+  // partial sums to part[z][n][m] for right_mul_sum
+  const int kb = blockIdx.z * kper, ke = min(l, kb + kper);
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k0 = 0; k0 < l; k0 += kMK) {
+  for (int k0 = kb; k0 < ke; k0 += kMK) {
     for (int e = t; e < kMR * kMK; e += 256) {
       const int a = e / kMK, b = e % kMK;
       const int64_t row = row0 + a;
-      sa[a][b] = (row < n && k0 + b < l) ? (double)A[row * lda + k0 + b] : 0.0;
+      sa[a][b] = (row < n && k0 + b < ke) ? (double)A[row * lda + k0 + b] : 0.0;
     }
     for (int e = t; e < kMK * kMC; e += 256) {
       const int a = e / kMC, b = e % kMC;
-      sm[a][b] = (k0 + a < l && c0 + b < m) ? M[(int64_t)(k0 + a) * m + c0 + b] : 0.0;
+      sm[a][b] = (k0 + a < ke && c0 + b < m) ? M[(int64_t)(k0 + a) * m + c0 + b] : 0.0;
     }
     __syncthreads();
     for (int k = 0; k < kMK; ++k) {
@@ -169,10 +173,28 @@ __global__ __launch_bounds__(256) void right_mul(int64_t n, int l, const T *A, i
     for (int q = 0; q < 8; ++q) {
       const int c = c0 + cc + q;
       if (c < m) {
-        const double base = Cin ? (double)Cin[row * ldc + c] : 0.0;
-        out[row * ldo + c] = (T)(base + acc[q]);
+        if (part) {
+          part[((int64_t)blockIdx.z * n + row) * m + c] = acc[q];
+        } else {
+          const double base = Cin ? (double)Cin[row * ldc + c] : 0.0;
+          out[row * ldo + c] = (T)(base + acc[q]);
+        }
       }
     }
+}
+
+// out = Cin + the nz partial products of a split right_mul, summed in split order.
+template <typename T>
+__global__ void right_mul_sum(int64_t n, int m, int nz, const double *part, const T *Cin,
+                              int64_t ldc, T *out, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * m) return;
+  const int64_t row = e / m;
+  const int c = (int)(e - row * m);
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += part[(int64_t)z * n * m + e];
+  const double base = Cin ? (double)Cin[row * ldc + c] : 0.0;
+  out[row * ldo + c] = (T)(base + s);
 }
 
 template <typename T>
@@ -348,11 +370,36 @@ hipError_t gram(int64_t n, int l1, const T *A, int64_t lda, int l2, const T *B, 
   return hipGetLastError();
 }
 
+// Splits of the inner dimension for a small right multiplication (about 512 blocks in all, at
+// least 64 terms each, at most kMulSplitMax; a 3000 x 500 by 15 product ran 47 blocks, 94 us),
+// and the partial-product doubles they need.
+constexpr int kMulSplitMax = 8;
+constexpr int64_t kMulSplitRows = 8192;  // larger n: enough blocks without a split
+int mul_splits(int64_t n, int l, int m) {
+  const int64_t blocks = ((n + kMR - 1) / kMR) * ((m + kMC - 1) / kMC);
+  if (n > kMulSplitRows || blocks >= 256) return 1;
+  int64_t z = std::min<int64_t>(kMulSplitMax, (512 + blocks - 1) / blocks);
+  z = std::min<int64_t>(z, std::max<int64_t>(1, l / 64));
+  return (int)std::max<int64_t>(1, z);
+}
+size_t mul_split_doubles(int64_t n, int l, int m) {
+  const int z = mul_splits(n, l, m);
+  return z > 1 ? (size_t)z * n * m : 0;
+}
+
+// out = Cin + A M (A n x l, M l x m); split over l into `split` (mul_split_doubles scratch) when
+// that is given and the product is small.
 template <typename T>
 hipError_t rmul(int64_t n, int l, const T *A, int64_t lda, const double *M, int m, const T *Cin,
-                int64_t ldc, T *out, int64_t ldo, hipStream_t s) {
-  right_mul<T><<<dim3((unsigned)((n + kMR - 1) / kMR), (unsigned)((m + kMC - 1) / kMC)), 256, 0, s>>>(
-      n, l, A, lda, M, m, Cin, ldc, out, ldo);
+                int64_t ldc, T *out, int64_t ldo, hipStream_t s, double *split = nullptr) {
+  const int z = split ? mul_splits(n, l, m) : 1;
+  const int kper = z > 1 ? (((l + z - 1) / z + kMK - 1) / kMK) * kMK : l;
+  const int nz = (l + kper - 1) / kper;
+  right_mul<T><<<dim3((unsigned)((n + kMR - 1) / kMR), (unsigned)((m + kMC - 1) / kMC), (unsigned)nz),
+                 256, 0, s>>>(n, l, A, lda, M, m, Cin, ldc, out, ldo, kper, nz > 1 ? split : nullptr);
+  if (nz > 1)
+    right_mul_sum<T><<<(unsigned)((n * m + 255) / 256), 256, 0, s>>>(n, m, nz, split, Cin, ldc, out,
+                                                                    ldo);
   return hipGetLastError();
 }
 
@@ -788,7 +835,8 @@ bool ranges_overlap(const void *a, int64_t rows, int64_t lda, int cols, const vo
 
 size_t nystrom_apply_scratch(int64_t n, int rank, int r) {
   return align256(sizeof(double) * (size_t)gram_part_doubles(n, rank, r)) +
-         2 * align256(sizeof(double) * (size_t)rank * r);
+         2 * align256(sizeof(double) * (size_t)rank * r) +
+         align256(sizeof(double) * mul_split_doubles(n, rank, r));
 }
 
 template <typename T>
@@ -798,11 +846,12 @@ hipError_t nystrom_apply(int64_t n, int rank, const T *U, const double *lam, con
   double *gpart = (double *)scratch;
   double *tkc = (double *)(scratch + align256(sizeof(double) * (size_t)gram_part_doubles(n, rank, r)));
   double *M = tkc + align256(sizeof(double) * (size_t)rank * r) / sizeof(double);
+  double *split = M + align256(sizeof(double) * (size_t)rank * r) / sizeof(double);
   hipError_t e = gram<T>(n, rank, U, rank, r, v, r, gpart, tkc, s);
   if (e != hipSuccess) return e;
   pcg_prec_scale<<<(unsigned)((rank * r + 255) / 256), 256, 0, s>>>(rank, r, lam, theta, nth, shift,
                                                                     tkc, M);
-  return rmul<T>(n, rank, U, rank, M, r, v, r, z, r, s);
+  return rmul<T>(n, rank, U, rank, M, r, v, r, z, r, s, split);
 }
 
 template hipError_t nystrom_apply<float>(int64_t, int, const float *, const double *,
