@@ -8,7 +8,11 @@
 namespace gpk {
 
 // Jobs a chain can publish; every job is split into n_rb row blocks x n_cs column splits.
-enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3, kJobZ = 4, kJobStage = 5 };
+// kJobGather: preconditioned chains with column splits in a persistent launch, after a product
+// job (gsrc = kJobMvX or kJobMvP): q from the split partials, v . q and the preconditioner's
+// partials, one row block per job id.
+enum HmcJob { kJobNone = 0, kJobMvX = 1, kJobMvP = 2, kJobQf = 3, kJobZ = 4, kJobStage = 5,
+              kJobGather = 6 };
 // Why the current solve + quadratic-form pass is being done.
 enum HmcCtxKind { kCtxEnergy0 = 0, kCtxForce = 1, kCtxEnergy1 = 2 };
 
@@ -76,6 +80,7 @@ struct HmcChain {
   const double *plam;
   int prank;
   int zfirst;     // the pending z job starts a solve (p = z) rather than continuing it
+  int gsrc;       // the product job a pending gather job completes (kJobMvX or kJobMvP)
   double *pgp, *pg, *ph;
   double centre[kMaxD];
   // schedule

@@ -100,9 +100,11 @@ int plain_splits(int64_t n) {
 // and force-pass job's columns (at most kMaxSplits ways, at least kMinSplitCols columns each)
 // until it has about that many, so a few chains still fill the GPU (one FP64 row-block job of a
 // 3000-point chain is ~150 us of one workgroup).  Not for GP_BF16X chains (their jobs take no
-// splits) or preconditioned launches (their row-block partials of U^T w come from the complete
-// q).  The split partials are summed in the chain's epilogue, whose latency grows with the
-// split count: on 10 FP64 chains of 3000 points a multi-shift iteration took 429 / 263 / 204 /
+// splits).  The split partials are summed in the chain's epilogue, or for preconditioned chains
+// (whose row-block partials of U^T w need the complete q) by a gather job over the row blocks,
+// which costs a scheduling round per CG iteration and so is used only from kMinPcSplits splits
+// on (with 2 splits the 32-chain float batch ran 170 -> 137 chain-steps/s).  The epilogue's
+// latency grows with the split count: on 10 FP64 chains of 3000 points a multi-shift iteration took 429 / 263 / 204 /
 // 287 / 333 / 370 us with at most 1 / 2 / 4 / 6 / 8 / 16 splits, a CG iteration 379 / 209 / 224 /
 // 230 / 259 / 312 us.  The target: 32 float chains of 6k-19k points (about 1,500 row blocks) ran
 // 20-step trajectories at 107.7 / 137.6 / 130.7 / 126.1 chain-steps/s with 1 / 2 / 3 / 4 splits
@@ -110,15 +112,16 @@ int plain_splits(int64_t n) {
 constexpr int64_t kSplitTarget = 4096;
 constexpr int kMaxSplits = 4;
 constexpr int64_t kMinSplitCols = 256;
+constexpr int kMinPcSplits = 4;
 
 int persistent_splits(const std::vector<InstInfo> &inst, int chains, int prec, int prank) {
-  if (prank > 0) return 1;
   int64_t jobs = 0;
   for (const InstInfo &in : inst) {
     if (xm_width(prec, in.d)) return 1;
     jobs += row_blocks(in.n, 0) * chains;
   }
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplits, kSplitTarget / std::max<int64_t>(1, jobs)));
+  const int s = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplits, kSplitTarget / std::max<int64_t>(1, jobs)));
+  return prank > 0 && s < kMinPcSplits ? 1 : s;
 }
 
 // Per-chain workspace; np > 0: a refresh of phi with np poles (shifted directions and pole state).
@@ -505,9 +508,10 @@ static gp_status run_chains(const gp_kernel *k, const gp_hmc_params *p, const gp
   prm.dt = p->dt;
   prm.tol2 = p->cg_tol * p->cg_tol;
   prm.cg_maxit = p->cg_maxit;
-  // a preconditioned CG iteration is two jobs (the product and the z job); a solve adds its
-  // first product, the force pass and (GP_BF16X) the stage job
-  const int64_t per_it = p->precond_rank > 0 ? 2 : 1;
+  // a preconditioned CG iteration is two or three jobs (the product, with split columns in a
+  // persistent launch the gather job, and the z job); a solve adds its first product and gather,
+  // the force pass and (GP_BF16X) the stage job
+  const int64_t per_it = p->precond_rank > 0 ? 3 : 1;
   prm.max_jobs = (int)std::min<int64_t>((int64_t)(prm.n_steps + 2) * (per_it * p->cg_maxit + 4) + 4,
                                         (int64_t)1 << 30);
   prm.rwm = rwm;
