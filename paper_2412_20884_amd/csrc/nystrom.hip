@@ -8,7 +8,7 @@
 //     Y = K Q                    gp_kmatvec with GP_NO_NOISE, l right-hand sides
 //     nu = sqrt(n) eps |Y|_F     Y_nu = Y + nu Q
 //     C^T C = Q^T Y_nu,  B = Y_nu C^{-1}
-//     B = U S V^T                from the l x l eigendecomposition of B^T B (cyclic Jacobi on the
+//     B = U S V^T                from the l x l eigendecomposition of B^T B (Householder + QL on the
 //                                host): U = B V S^{-1}
 //     lam = max(0, S^2 - nu),    K ~ U diag(lam) U^T.
 // Preconditioner for A + lambda I = K + mu I (mu = sigma^2 + lambda, so one factor serves every
@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "common.h"
@@ -250,53 +251,114 @@ void inv_upper(const std::vector<double> &C, int l, std::vector<double> &Ci) {
   }
 }
 
-// Eigenvalues (descending) and eigenvectors (columns of V) of a symmetric matrix by cyclic
-// Jacobi rotations.
-void jacobi_eig(std::vector<double> S, int l, std::vector<double> &ev, std::vector<double> &V) {
-  V.assign((size_t)l * l, 0.0);
-  for (int i = 0; i < l; ++i) V[(size_t)i * l + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < l; ++i)
-      for (int j = 0; j < l; ++j) {
-        const double v = S[(size_t)i * l + j] * S[(size_t)i * l + j];
-        tot += v;
-        if (i != j) off += v;
+// Eigenvalues (descending) and orthonormal eigenvectors (columns of V, row-major l x l) of a
+// symmetric matrix: Householder reduction to tridiagonal form T = Q^T S Q, then the implicit
+// shifted QL iteration on T (Wilkinson-type shift from the leading 2 x 2 block of the active
+// part), each plane rotation applied to the accumulated Q.
+void sym_eig(std::vector<double> S, int l, std::vector<double> &ev, std::vector<double> &V) {
+  const int n = l;
+  std::vector<double> Q((size_t)n * n, 0.0), d(n), e(n, 0.0), v(n), p(n), w(n);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  auto A = [&](int i, int j) -> double & { return S[(size_t)i * n + j]; };
+  // Householder: for column k, reflect rows k+1..n-1 so that A(k+2.., k) = 0
+  for (int k = 0; k + 2 < n; ++k) {
+    double sig = 0.0;
+    for (int i = k + 1; i < n; ++i) sig += A(i, k) * A(i, k);
+    const double xn = std::sqrt(sig);
+    if (xn == 0.0) continue;
+    const double x0 = A(k + 1, k);
+    const double alpha = x0 > 0.0 ? -xn : xn;
+    // v = x - alpha e1, unit length
+    double vn2 = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      v[i] = A(i, k) - (i == k + 1 ? alpha : 0.0);
+      vn2 += v[i] * v[i];
+    }
+    if (vn2 == 0.0) continue;
+    const double inv = 1.0 / std::sqrt(vn2);
+    for (int i = k + 1; i < n; ++i) v[i] *= inv;
+    // H A H on rows/columns k.. with H = I - 2 v v^T (v zero above k+1): p = A v over the
+    // trailing block (and row k), K = v^T p, w = p - K v, A -= 2 (v w^T + w v^T)
+    for (int i = k; i < n; ++i) {
+      double t = 0.0;
+      for (int j = k + 1; j < n; ++j) t += A(i, j) * v[j];
+      p[i] = t;
+    }
+    double K = 0.0;
+    for (int i = k + 1; i < n; ++i) K += v[i] * p[i];
+    for (int i = k; i < n; ++i) w[i] = p[i] - (i > k ? K * v[i] : 0.0);
+    for (int i = k; i < n; ++i) {
+      const double vi = i > k ? v[i] : 0.0;
+      for (int j = k; j < n; ++j) {
+        const double vj = j > k ? v[j] : 0.0;
+        A(i, j) -= 2.0 * (vi * w[j] + w[i] * vj);
       }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < l - 1; ++p)
-      for (int q = p + 1; q < l; ++q) {
-        const double apq = S[(size_t)p * l + q];
-        if (fabs(apq) < 1e-300) continue;
-        const double app = S[(size_t)p * l + p], aqq = S[(size_t)q * l + q];
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int k = 0; k < l; ++k) {  // rows p, q
-          const double a = S[(size_t)p * l + k], b = S[(size_t)q * l + k];
-          S[(size_t)p * l + k] = c * a - s * b;
-          S[(size_t)q * l + k] = s * a + c * b;
+    }
+    // Q <- Q H
+    for (int r = 0; r < n; ++r) {
+      double t = 0.0;
+      for (int j = k + 1; j < n; ++j) t += Q[(size_t)r * n + j] * v[j];
+      t *= 2.0;
+      for (int j = k + 1; j < n; ++j) Q[(size_t)r * n + j] -= t * v[j];
+    }
+  }
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);  // e[i] couples i and i + 1
+  // implicit QL: deflate from the top; the active block is lo..m with e[m] negligible
+  for (int lo = 0; lo < n; ++lo) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = lo;
+      for (; m + 1 < n; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-16 * dd) break;
+      }
+      if (m == lo) break;
+      // shift: the eigenvalue of the leading 2 x 2 block [d_lo e_lo; e_lo d_lo+1] nearer d_lo
+      double g = (d[lo + 1] - d[lo]) / (2.0 * e[lo]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[lo] + e[lo] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      int i = m - 1;
+      bool early = false;
+      for (; i >= lo; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // underflow: the block splits here
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          early = true;
+          break;
         }
-        for (int k = 0; k < l; ++k) {  // columns p, q
-          const double a = S[(size_t)k * l + p], b = S[(size_t)k * l + q];
-          S[(size_t)k * l + p] = c * a - s * b;
-          S[(size_t)k * l + q] = s * a + c * b;
-          const double va = V[(size_t)k * l + p], vb = V[(size_t)k * l + q];
-          V[(size_t)k * l + p] = c * va - s * vb;
-          V[(size_t)k * l + q] = s * va + c * vb;
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {  // rotate columns i, i + 1 of Q
+          const double qa = Q[(size_t)k * n + i], qb = Q[(size_t)k * n + i + 1];
+          Q[(size_t)k * n + i + 1] = s * qa + c * qb;
+          Q[(size_t)k * n + i] = c * qa - s * qb;
         }
       }
+      if (early) continue;
+      d[lo] -= pp;
+      e[lo] = g;
+      e[m] = 0.0;
+    }
   }
-  std::vector<int> idx(l);
-  for (int i = 0; i < l; ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return S[(size_t)a * l + a] > S[(size_t)b * l + b]; });
-  std::vector<double> V2((size_t)l * l);
-  ev.resize(l);
-  for (int j = 0; j < l; ++j) {
-    ev[j] = S[(size_t)idx[j] * l + idx[j]];
-    for (int i = 0; i < l; ++i) V2[(size_t)i * l + j] = V[(size_t)i * l + idx[j]];
+  // descending order
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] > d[b]; });
+  ev.resize(n);
+  V.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    ev[j] = d[idx[j]];
+    for (int k = 0; k < n; ++k) V[(size_t)k * n + j] = Q[(size_t)k * n + idx[j]];
   }
-  V = V2;
 }
 
 // ---- workspace helpers ------------------------------------------------------------------------
@@ -523,7 +585,7 @@ gp_status run_nystrom(const gp_kernel *k, int64_t n, const void *X, const double
   st = to_host(hG, G, (size_t)l * l, s);
   if (st) return st;
   std::vector<double> ev, V;
-  jacobi_eig(hG, l, ev, V);
+  sym_eig(hG, l, ev, V);
   std::vector<double> hM((size_t)l * l), hl(l);
   for (int j = 0; j < l; ++j) {
     const double s2 = ev[j] > 0.0 ? ev[j] : 0.0;
