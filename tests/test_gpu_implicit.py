@@ -91,6 +91,15 @@ def test_implicit_float32_nystrom_endpoints_and_flags():
     assert int(r2["status"][0]) & gpk.CHAIN_FP_MAXIT and int(r2["accepted"][0]) == 0
     np.testing.assert_array_equal(host(thd2), th)
     np.testing.assert_array_equal(host(pid2), pi0)
+    # the iterations run as replays of a captured group of four: a limit that is not a multiple
+    # of four still stops at the limit (2, then 6 = one group and half of the next)
+    assert int(r2["iters"][0]) == 2
+    r3 = gpk.hmc_implicit(Xd, to_dev(y, torch.float32), to_dev(phi, torch.float32),
+                          to_dev(th, torch.float64), to_dev(pi0, torch.float64),
+                          torch.zeros(1500, dtype=torch.float32, device="cuda:0"), "iso", n_steps=2,
+                          dt=0.05, history=10, tol=1e-12, maxit=6, cg_tol=1e-6)
+    torch.cuda.synchronize()
+    assert int(r3["status"][0]) & gpk.CHAIN_FP_MAXIT and int(r3["iters"][0]) == 6
 
 
 def test_implicit_cheb_kernel():

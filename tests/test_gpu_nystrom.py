@@ -124,3 +124,7 @@ def test_pcg_warm_start_and_maxit():
     torch.cuda.synchronize()
     assert np.all(host(warm["iters"]) == 0) and np.all(host(warm["status"]) == 0)
     assert np.all(host(short["status"]) == gpk.CG_MAXIT) and np.all(host(short["iters"]) == 3)
+    # a replayed group of four iterations and three single ones: still exactly the limit
+    seven = gpk.pcg_solve(Xd, thd, Bd, "iso", tol=1e-14, maxit=7)
+    torch.cuda.synchronize()
+    assert np.all(host(seven["status"]) == gpk.CG_MAXIT) and np.all(host(seven["iters"]) == 7)

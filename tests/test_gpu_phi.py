@@ -101,6 +101,11 @@ def test_phi_maxit_flag_and_iterations():
     torch.cuda.synchronize()
     assert np.all(host(res["status"]) == gpk.PHI_CG_MAXIT)
     assert np.all(host(res["iters"]) == 3)
+    # a replayed group of four iterations and two single ones: still exactly the limit
+    res6 = gpk.phi_refresh(Xd, thd, xid, "iso", tol=1e-13, maxit=6)
+    torch.cuda.synchronize()
+    assert np.all(host(res6["status"]) == gpk.PHI_CG_MAXIT)
+    assert np.all(host(res6["iters"]) == 6)
     full = gpk.phi_refresh(Xd, thd, xid, "iso", tol=1e-10, maxit=5000)
     torch.cuda.synchronize()
     it = host(full["iters"])
