@@ -9,7 +9,9 @@ of P(theta) on the paper's 100^2 grid (trapezoid rule), written from the oracle'
 posterior.
 
 500 chains (the paper's B) run Algorithm 1 on the device: per update, phi | theta is drawn
-exactly (phi = L^{-T} xi with A = L L^T, on the host), pi ~ N(0, I), and one graph-replayed
+exactly (phi = L^{-T} xi with A = L L^T, on the host) or, in the third case, by the device's
+Gibbs refresh of every chain at its own theta (gp_phi_refresh_chains: the pole expansion of
+Section 3.1 with multi-shift CG, one graph-replayed launch), pi ~ N(0, I), and one graph-replayed
 leapfrog trajectory of N_int = 3 steps of 0.4 (the paper's E1 leapfrog settings) with the
 Metropolis decision on the device; the diagonal inverse mass holds the fixed hyperparameters
 still (a zero entry), and a proposal outside the box is rejected by the caller (the box prior).
@@ -51,8 +53,8 @@ def _e1():
     return spec, X, y, axis, gold, gold_cheb, make_golden.cheb_base(spec)
 
 
-@pytest.mark.parametrize("kind", ["cheb", "iso"])
-def test_e1_marginals_within_dkw_radius(kind):
+@pytest.mark.parametrize("kind,refresh", [("cheb", "host"), ("iso", "host"), ("cheb", "device")])
+def test_e1_marginals_within_dkw_radius(kind, refresh):
     spec, X, y, axis, gold_iso, gold_cheb, cheb_base = _e1()
     n = len(y)
     B, burn, keep = 500, 20, 200
@@ -87,13 +89,22 @@ def test_e1_marginals_within_dkw_radius(kind):
     samples = np.empty((keep, B, 2))
     acc_total = 0
     r = None  # the first call's outputs are passed back: later graph launches replay the capture
+    rf = None
+    xid = torch.zeros(B * n, dtype=torch.float64, device=DEV)
     for it in range(burn + keep):
         th_host = host(thd).reshape(B, nt)
-        phi = np.empty((B, n))
-        for b in range(B):
-            Lc = np.linalg.cholesky(ogp.a_matrix(X, th_host[b], kind))
-            phi[b] = np.linalg.solve(Lc.T, g.standard_normal(n))
-        phid.copy_(torch.from_numpy(phi.ravel()))
+        if refresh == "host":
+            phi = np.empty((B, n))
+            for b in range(B):
+                Lc = np.linalg.cholesky(ogp.a_matrix(X, th_host[b], kind))
+                phi[b] = np.linalg.solve(Lc.T, g.standard_normal(n))
+            phid.copy_(torch.from_numpy(phi.ravel()))
+        else:
+            xid.copy_(torch.from_numpy(g.standard_normal(B * n)))
+            rf = gpk.phi_refresh_chains(Xd, thd, xid, kind, [n], [0], B, tol=1e-12, maxit=500,
+                                        mode=gpk.GRAPH, n_cheb=n_cheb, out=phid, outputs=rf)
+            torch.cuda.synchronize()
+            assert np.all(rf["status"].cpu().numpy() == 0)
         pid.copy_(torch.from_numpy(g.standard_normal(nt * B)))
         ud.copy_(torch.from_numpy(g.uniform(size=B)))
         r = gpk.hmc_leapfrog(Xd, yd, phid, thd, pid, xd, kind, [n], [0], B, u=ud, n_steps=3,
@@ -122,7 +133,7 @@ def test_e1_marginals_within_dkw_radius(kind):
         emp = np.searchsorted(s, axis, side="right") / s.size
         err = float(np.max(np.abs(emp - cdf_gold[k])))
         report.append((k, tau, n_eff, radius, err))
-        print(f"E1 {kind} component {k}: tau {tau:.2f}, n_eff {n_eff:.0f}, sup CDF error {err:.4f}, "
+        print(f"E1 {kind} ({refresh} refresh) component {k}: tau {tau:.2f}, n_eff {n_eff:.0f}, sup CDF error {err:.4f}, "
               f"DKW radius {radius:.4f}, acceptance {rate:.3f}")
     assert 0.3 < rate < 0.98
     for k, tau, n_eff, radius, err in report:
