@@ -4,13 +4,16 @@ The oracle computes sampled rows one by one (all N columns each); sums over all 
 checked through identities that hold at any size, and the theta-gradient element by element on
 a row sample (the left operand zeroed outside it, so the gradient is the oracle's
 row-restricted one).  The batched trajectories are checked for exact agreement between the
-graph replay and the persistent launch, and against the plain single-chain form.
+graph replay and the persistent launch, and against the plain single-chain form.  The cheb2d
+workload (N = 3000, FP64) is small enough for the oracle's dense Cholesky path at full size.
 """
 import numpy as np
 import pytest
 import torch
 
 from oracle import gp as ogp
+from oracle import hmc as ohmc
+from oracle import poles as opoles
 from paper_2412_20884_amd import gpk, inputs as I
 from tests.gpu_util import DEV, comp_rel_err, grad_rel_err, host, rounded, to_dev
 
@@ -160,3 +163,113 @@ def test_batched_trajectories_graph_persistent_plain():
     # the energies differ by float32 summation order only
     assert np.all(np.abs(g["H1"] - g["H0"] - (p["H1"] - p["H0"])) <= 2e-6 * np.abs(p["H0"]) + 1e-3)
     assert np.all(np.abs(g["cg"] - p["cg"]) <= 0.02 * p["cg"] + 2)
+
+
+def test_batched_refresh_one_launch_full_size():
+    """The benchmark's one-launch refresh: every chain of every 16th instance of the batched
+    workload (N_b = 7018, 19409, 11616, 6050; 8 chains each, each its own system) in one
+    batched-mode gp_phi_refresh_chains launch, FP32, tolerance 1e-6.  The smallest instance's 8
+    chains against the oracle's pole expansion (Cholesky shifted solves, same m and M).  Bound: the
+    shifted solves' residuals give a relative error <= tol sqrt(M / m) (twice that for the
+    recurrence residual's drift), and float32 entries and products (M / m) eps32 (ten times
+    that, as in the batched refresh tests)."""
+    wl = I.batched()
+    C = wl["chains"]
+    inst = wl["instances"][::16]
+    ns = [b["X"].shape[0] for b in inst]
+    ds = [b["X"].shape[1] for b in inst]
+    offs = [int(o) for o in np.cumsum([0] + ns[:-1])]
+    xoffs = [int(o) for o in np.cumsum([0] + [a * b for a, b in zip(ns, ds)][:-1])]
+    X = to_dev(np.concatenate([b["X"].ravel() for b in inst]), torch.float32)[:, None]
+    xi = np.concatenate([b["xi"].ravel() for b in inst])
+    th = np.concatenate([np.tile(b["theta"], C) for b in inst])
+    tol = 1e-6
+    r = gpk.phi_refresh_chains(X, to_dev(th, torch.float64), to_dev(xi, torch.float32), "ard", ns,
+                               offs, C, d=ds, x_offsets=xoffs, tol=tol, maxit=3000,
+                               mode=gpk.BATCHED)
+    torch.cuda.synchronize()
+    assert np.all(host(r["status"]) == 0)
+    bi = int(np.argmin(ns))
+    b, n = inst[bi], ns[bi]
+    Xr = rounded(b["X"], torch.float32)
+    bounds = host(r["bounds"]).reshape(-1, 2)[bi * C:(bi + 1) * C]
+    m, M = bounds[0]
+    assert np.all(bounds == bounds[0])
+    assert m == pytest.approx(np.exp(b["theta"][-1]), rel=1e-15)
+    M_ref = opoles.gershgorin_upper(Xr, b["theta"], "ard")
+    assert M_ref <= M <= M_ref * (1 + 1e-4)  # widened past the float32 row sums' rounding
+    ref = opoles.inv_sqrt_apply(Xr, b["theta"], "ard", rounded(b["xi"], torch.float32).T, M=M)
+    phi = host(r["phi"])[C * offs[bi]:C * (offs[bi] + n)].reshape(C, n)
+    bound = 2.0 * tol * np.sqrt(M / m) + 10 * (M / m) * 2.0 ** -24
+    errs = [np.linalg.norm(phi[c] - ref[:, c]) / np.linalg.norm(ref[:, c]) for c in range(C)]
+    print(f"batched refresh, N = {n}: max rel err {max(errs):.3e}, bound {bound:.3e}, "
+          f"iterations {host(r['iters']).max()}")
+    assert max(errs) < bound, (errs, bound)
+
+
+def test_cheb2d_full_size_refresh_and_trajectories():
+    """The cheb2d workload at full size (N = 3000 points in [-1, 1]^2, Chebyshev-amplitude SE with
+    N_cheb = 4, FP64, 10 chains), launched as the benchmark's plain-CG run launches it: the 10
+    chains' phi in one graph-mode gp_phi_refresh_chains launch, then their trajectories (3
+    leapfrog steps of 0.03, update 0's pi and u) in one graph-mode gp_hmc_leapfrog launch.
+
+    phi against the oracle's pole expansion with Cholesky shifted solves (same m and M), at the
+    benchmark's tolerance and at a tight one.  Bound: each shifted system (A + lambda_p) x_p = xi
+    stops at residual <= tol |xi| and A + lambda_p >= (m + lambda_p) I, so
+    |delta phi| <= tol |xi| sum_p w_p / (m + lambda_p) ~ tol |xi| / sqrt(m), while
+    |phi| >= |xi| / sqrt(M): relative error <= tol sqrt(M / m) (a factor 2 for the recurrence
+    residual's drift).  Trajectories from the oracle's phi, CG at 1e-12, against the oracle's
+    leapfrog with exact solves (one chain accepted, one rejected)."""
+    wl = I.cheb2d()
+    X, y, th0 = wl["X"], wl["y"], wl["theta"]
+    n, C, nc = X.shape[0], wl["chains"], wl["n_cheb"]
+    Xd = to_dev(X, torch.float64).reshape(-1, 1)
+    xi = wl["xi"][0]  # (C, n): chain c's xi at c * n
+    M_ref = opoles.gershgorin_upper(X, th0, "cheb")
+    ref = opoles.inv_sqrt_apply(X, th0, "cheb", xi.T, M=M_ref * (1 + 1e-12))
+    for tol in (1e-6, 1e-11):
+        r = gpk.phi_refresh_chains(Xd, to_dev(np.tile(th0, C), torch.float64),
+                                   to_dev(xi.ravel(), torch.float64), "cheb", [n], [0], C, d=[2],
+                                   tol=tol, maxit=5000, n_cheb=nc, mode=gpk.GRAPH)
+        torch.cuda.synchronize()
+        assert np.all(host(r["status"]) == 0), tol
+        bounds = host(r["bounds"]).reshape(-1, 2)
+        m, M = bounds[0]
+        assert np.all(bounds == bounds[0])
+        assert M == pytest.approx(M_ref * (1 + 1e-12), rel=1e-12)
+        phi = host(r["phi"]).reshape(C, n)
+        bound = 2.0 * tol * np.sqrt(M / m) + 1e-13
+        errs = [np.linalg.norm(phi[c] - ref[:, c]) / np.linalg.norm(ref[:, c]) for c in range(C)]
+        print(f"cheb2d refresh tol {tol:g}: max rel err {max(errs):.3e}, bound {bound:.3e}, "
+              f"iterations {host(r['iters']).max()}")
+        assert max(errs) < bound, (tol, errs, bound)
+
+    dt, ns = wl["dt"], wl["n_steps"]
+    pi0, u = wl["pi"][0], wl["u"][0]
+    thd = to_dev(np.tile(th0, C), torch.float64)
+    pid = to_dev(pi0.ravel(), torch.float64)
+    x = torch.zeros(n * C, dtype=torch.float64, device=DEV)
+    res = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float64), to_dev(ref.T.ravel(), torch.float64), thd,
+                           pid, x, "cheb", [n], [0], C, d=[2], u=to_dev(u, torch.float64),
+                           n_steps=ns, dt=dt, cg_tol=1e-12, cg_maxit=5000, mode=gpk.GRAPH,
+                           n_cheb=nc)
+    torch.cuda.synchronize()
+    nt = len(th0)
+    th_out, pi_out = host(thd).reshape(C, nt), host(pid).reshape(C, nt)
+    decisions = set()
+    for c in (0, C - 1):
+        th1, pi1 = ohmc.leapfrog(X, "cheb", y, ref[:, c], th0, pi0[c], dt, ns)
+        H0 = ohmc.hamiltonian(X, th0, "cheb", y, ref[:, c], pi0[c])
+        H1 = ohmc.hamiltonian(X, th1, "cheb", y, ref[:, c], pi1)
+        acc = ohmc.accept(H0, H1, u[c])
+        decisions.add(acc)
+        assert int(res["status"][c]) == 0
+        assert float(res["H0"][c]) == pytest.approx(H0, rel=1e-10)
+        assert float(res["H1"][c]) == pytest.approx(H1, rel=1e-9)
+        assert bool(res["accepted"][c]) == acc
+        print(f"cheb2d chain {c}: accepted {acc}, |theta - oracle| "
+              f"{np.max(np.abs(th_out[c] - (th1 if acc else th0))):.3e}, |pi - oracle| "
+              f"{np.max(np.abs(pi_out[c] - (pi1 if acc else pi0[c]))):.3e}")
+        assert np.max(np.abs(th_out[c] - (th1 if acc else th0))) < 1e-8
+        assert np.max(np.abs(pi_out[c] - (pi1 if acc else pi0[c]))) < 1e-8
+    assert decisions == {True, False}
