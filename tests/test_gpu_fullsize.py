@@ -218,8 +218,9 @@ def test_cheb2d_full_size_refresh_and_trajectories():
     stops at residual <= tol |xi| and A + lambda_p >= (m + lambda_p) I, so
     |delta phi| <= tol |xi| sum_p w_p / (m + lambda_p) ~ tol |xi| / sqrt(m), while
     |phi| >= |xi| / sqrt(M): relative error <= tol sqrt(M / m) (a factor 2 for the recurrence
-    residual's drift).  Trajectories from the oracle's phi, CG at 1e-12, against the oracle's
-    leapfrog with exact solves (one chain accepted, one rejected)."""
+    residual's drift).  Trajectories from the oracle's phi, CG at 1e-12, plain and with the
+    benchmark's rank-500 Nystrom preconditioner, against the oracle's leapfrog with exact solves
+    (one chain accepted, one rejected)."""
     wl = I.cheb2d()
     X, y, th0 = wl["X"], wl["y"], wl["theta"]
     n, C, nc = X.shape[0], wl["chains"], wl["n_cheb"]
@@ -246,30 +247,38 @@ def test_cheb2d_full_size_refresh_and_trajectories():
 
     dt, ns = wl["dt"], wl["n_steps"]
     pi0, u = wl["pi"][0], wl["u"][0]
-    thd = to_dev(np.tile(th0, C), torch.float64)
-    pid = to_dev(pi0.ravel(), torch.float64)
-    x = torch.zeros(n * C, dtype=torch.float64, device=DEV)
-    res = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float64), to_dev(ref.T.ravel(), torch.float64), thd,
-                           pid, x, "cheb", [n], [0], C, d=[2], u=to_dev(u, torch.float64),
-                           n_steps=ns, dt=dt, cg_tol=1e-12, cg_maxit=5000, mode=gpk.GRAPH,
-                           n_cheb=nc)
-    torch.cuda.synchronize()
     nt = len(th0)
-    th_out, pi_out = host(thd).reshape(C, nt), host(pid).reshape(C, nt)
-    decisions = set()
+    # the benchmark's rank-500 factor at theta_0 (it changes iteration counts, not results)
+    omega = to_dev(I.rng(I.WORKLOAD_SEEDS["cheb2d"], I.P_V).standard_normal((n, 500)), torch.float64)
+    U, lam = gpk.nystrom(to_dev(X, torch.float64), to_dev(th0, torch.float64), omega, "cheb",
+                         n_cheb=nc)
+    oracle = {}
     for c in (0, C - 1):
         th1, pi1 = ohmc.leapfrog(X, "cheb", y, ref[:, c], th0, pi0[c], dt, ns)
         H0 = ohmc.hamiltonian(X, th0, "cheb", y, ref[:, c], pi0[c])
         H1 = ohmc.hamiltonian(X, th1, "cheb", y, ref[:, c], pi1)
-        acc = ohmc.accept(H0, H1, u[c])
-        decisions.add(acc)
-        assert int(res["status"][c]) == 0
-        assert float(res["H0"][c]) == pytest.approx(H0, rel=1e-10)
-        assert float(res["H1"][c]) == pytest.approx(H1, rel=1e-9)
-        assert bool(res["accepted"][c]) == acc
-        print(f"cheb2d chain {c}: accepted {acc}, |theta - oracle| "
-              f"{np.max(np.abs(th_out[c] - (th1 if acc else th0))):.3e}, |pi - oracle| "
-              f"{np.max(np.abs(pi_out[c] - (pi1 if acc else pi0[c]))):.3e}")
-        assert np.max(np.abs(th_out[c] - (th1 if acc else th0))) < 1e-8
-        assert np.max(np.abs(pi_out[c] - (pi1 if acc else pi0[c]))) < 1e-8
-    assert decisions == {True, False}
+        oracle[c] = (th1, pi1, H0, H1, ohmc.accept(H0, H1, u[c]))
+    assert {o[4] for o in oracle.values()} == {True, False}
+    iters = {}
+    for precond in (None, (U, lam)):
+        thd = to_dev(np.tile(th0, C), torch.float64)
+        pid = to_dev(pi0.ravel(), torch.float64)
+        x = torch.zeros(n * C, dtype=torch.float64, device=DEV)
+        res = gpk.hmc_leapfrog(Xd, to_dev(y, torch.float64), to_dev(ref.T.ravel(), torch.float64),
+                               thd, pid, x, "cheb", [n], [0], C, d=[2], u=to_dev(u, torch.float64),
+                               n_steps=ns, dt=dt, cg_tol=1e-12, cg_maxit=5000, mode=gpk.GRAPH,
+                               n_cheb=nc, precond=precond)
+        torch.cuda.synchronize()
+        th_out, pi_out = host(thd).reshape(C, nt), host(pid).reshape(C, nt)
+        iters[precond is None] = host(res["cg_iters"])
+        for c, (th1, pi1, H0, H1, acc) in oracle.items():
+            assert int(res["status"][c]) == 0
+            assert float(res["H0"][c]) == pytest.approx(H0, rel=1e-10)
+            assert float(res["H1"][c]) == pytest.approx(H1, rel=1e-9)
+            assert bool(res["accepted"][c]) == acc
+            dth = np.max(np.abs(th_out[c] - (th1 if acc else th0)))
+            dpi = np.max(np.abs(pi_out[c] - (pi1 if acc else pi0[c])))
+            print(f"cheb2d chain {c}, preconditioned {precond is not None}: accepted {acc}, "
+                  f"|theta - oracle| {dth:.3e}, |pi - oracle| {dpi:.3e}")
+            assert dth < 1e-8 and dpi < 1e-8
+    assert np.all(iters[False] < iters[True])

@@ -69,10 +69,13 @@ def _factor(X, th, kind, rank, dtype, seed):
     return host(U), host(lam)
 
 
+@pytest.mark.parametrize("rank", [24, 300])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("mode", MODES)
-def test_preconditioned_trajectories_match_oracle(dtype, mode):
-    chains, rank, steps, dt = 2, 24, 4, 0.02
+def test_preconditioned_trajectories_match_oracle(dtype, mode, rank):
+    """Ranks 24 and 300: the row-block passes over U give each thread one or two of its columns,
+    and the z job's lanes one or several 64-column strips of a row; ragged last row blocks."""
+    chains, steps, dt = 2, 4, 0.02
     specs = [("iso", 900, 2, 0.4), ("iso", 1300, 2, 0.25)]
     insts, Us, lams = [], [], []
     for s, (kind, n, d, ell) in enumerate(specs):
