@@ -351,14 +351,32 @@ __global__ __launch_bounds__(64) void imp_update(ImpDev s, int nth, double dt, d
     hfh[k] = ftp[k];
     s.hg[head * w + k] = gtp[k];
   }
-  // the new Gram row: lane j sums its x-part partials and the parameter parts' product
-  if (t < m_new) {
-    double u = 0.0;
-    for (int q = 0; q < nb; ++q) u += row_part[q * m_new + t];
-    const double *hfj = s.hf + t * w;
-    for (int k = 0; k < 2 * nth; ++k) u += ftp[k] * (t == head ? ftp[k] : hfj[k]);
-    s.G[head * kHistMax + t] = u;
-    s.G[t * kHistMax + head] = u;
+  // the new Gram row, entry j < m_new: the row blocks' x-part partials plus the parameter
+  // parts' product, spread over the lanes (every lane's loads in flight together), each entry
+  // then summed by the butterfly (fixed order)
+  double u[kHistMax];
+#pragma unroll
+  for (int j = 0; j < kHistMax; ++j) u[j] = 0.0;
+  for (int q = t; q < nb; q += 64) {
+#pragma unroll
+    for (int j = 0; j < kHistMax; ++j)
+      if (j < m_new) u[j] += row_part[q * m_new + j];
+  }
+  for (int k = t; k < 2 * nth; k += 64) {
+    const double fk = ftp[k];
+#pragma unroll
+    for (int j = 0; j < kHistMax; ++j)
+      if (j < m_new) u[j] += fk * (j == head ? fk : s.hf[j * w + k]);
+  }
+#pragma unroll
+  for (int j = 0; j < kHistMax; ++j) {
+    if (j < m_new) {
+      const double v = wave_sum(u[j]);
+      if (t == 0) {
+        s.G[head * kHistMax + j] = v;
+        s.G[j * kHistMax + head] = v;
+      }
+    }
   }
   __threadfence_block();
   __syncthreads();
