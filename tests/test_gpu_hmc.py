@@ -111,6 +111,43 @@ def test_batched_instances_match_oracle(dtype, mode):
             c += 1
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("mode", [gpk.PLAIN, gpk.GRAPH])
+def test_wide_instances_match_oracle(dtype, mode):
+    """ARD chains with d = 20 and d = 40 (padded widths 32 and 64): in plain mode their product
+    jobs run in the product-only tile kernel and the gradient passes in the shared one, in graph
+    mode every job in the persistent launch; length-scales in [2, 8] keep the off-diagonal
+    kernel values O(0.1), so the products are not nearly diagonal."""
+    chains = 2
+    insts = []
+    for s, (n, d) in enumerate([(520, 20), (450, 40)]):
+        p = I.ard_problem(n, d, 60 + s, lo=2.0, hi=8.0, sigma2=0.05)
+        X = rounded(p["X"], dtype)
+        y = rounded(p["y"], dtype)
+        g = np.random.default_rng(70 + s)
+        phis = [rounded(phi_exact(X, p["theta"], "ard", g.normal(size=n)), dtype) for _ in range(chains)]
+        pis = [0.3 * g.normal(size=d + 2) for _ in range(chains)]
+        insts.append({"X": X, "y": y, "theta": p["theta"], "phi": phis, "pi": pis,
+                      "x0": [np.zeros(n)] * chains})
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    steps, dt = 4, 0.02
+    r = run(insts, "ard", dtype, chains, steps, dt, tol, mode)
+    bound = 1e-8 if dtype == torch.float64 else 2e-4
+    pos = 0
+    c = 0
+    for b in insts:
+        nth = len(b["theta"])
+        for h in range(chains):
+            th1, pi1 = ohmc.leapfrog(b["X"], "ard", b["y"], b["phi"][h], b["theta"], b["pi"][h], dt, steps)
+            H1 = ohmc.hamiltonian(b["X"], th1, "ard", b["y"], b["phi"][h], pi1)
+            assert np.max(np.abs(r["theta"][pos:pos + nth] - th1)) < bound
+            assert np.max(np.abs(r["pi"][pos:pos + nth] - pi1)) < bound
+            assert abs(r["H1"][c] - H1) < (1e-8 if dtype == torch.float64 else 1e-4) * max(1.0, abs(H1))
+            assert r["status"][c] == 0
+            pos += nth
+            c += 1
+
+
 def test_accept_reject_and_restore():
     p = I.iso_problem(400, 2, 9, ell=0.3, sigma2=0.05)
     X, y, th = p["X"], p["y"], p["theta"]
